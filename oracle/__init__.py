@@ -1,0 +1,190 @@
+"""FP64 CPU oracle for the Oregonator stepper -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library
+(``paper_1901_06535_amd``) never imports, links or calls it, and it imports
+nothing from the product library: both sides share only the seeded input
+generators, which hold none of the method's arithmetic.
+
+The arithmetic lives in ``rdc_oracle.c`` (plain C, FP64, no contraction),
+following Sec. 2 / Eq. (1) / Table 1 of the paper; this module marshals numpy
+arrays into it and replays stimulus schedules.  Pins that tie it to the
+mathematics are in ``tests/test_oracle_pins.py`` and
+``tests/test_oracle_gates.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Iterable, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "rdc_oracle.c")
+LIB = os.path.join(HERE, "liboracle_rdc.so")
+NEVER = np.iinfo(np.int32).max
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: -O2, no fast-math, contraction off."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off",
+               "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("eps", "f", "q", "D_u", "dt", "dx")]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=False)
+        lib = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64 = ctypes.c_int64
+        lib.rdco_step.argtypes = [i64, i64, ctypes.POINTER(_Params), dp, dp, dp, dp, dp]
+        lib.rdco_step.restype = None
+        lib.rdco_euler_factor.argtypes = [ctypes.POINTER(_Params), ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double]
+        lib.rdco_euler_factor.restype = ctypes.c_double
+        lib.rdco_mark_arrival.argtypes = [i64, i64, dp, i32p, ctypes.c_double, i64]
+        lib.rdco_mark_arrival.restype = None
+        lib.rdco_stimulate.argtypes = [i64, i64, dp, ctypes.c_int32, i32p, i32p, i32p,
+                                       i32p, ctypes.c_double, i64]
+        lib.rdco_stimulate.restype = None
+        lib.rdco_run.argtypes = [i64, i64, ctypes.POINTER(_Params), dp, dp, dp, i64, i64,
+                                 i32p, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8),
+                                 i64, ctypes.POINTER(ctypes.c_int64)]
+        lib.rdco_run.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _params(p) -> _Params:
+    return _Params(*(float(p[k]) for k in ("eps", "f", "q", "D_u", "dt", "dx")))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def step(u, v, phi, params) -> Tuple[np.ndarray, np.ndarray]:
+    """One Euler step of Eq. (1); returns new (u, v) as float64 arrays."""
+    lib = _load()
+    u = _f64(u); v = _f64(v); phi = _f64(phi)
+    ny, nx = u.shape
+    un = np.empty_like(u); vn = np.empty_like(v)
+    p = _params(params)
+    lib.rdco_step(nx, ny, ctypes.byref(p), _ptr(u, ctypes.c_double), _ptr(v, ctypes.c_double),
+                  _ptr(phi, ctypes.c_double), _ptr(un, ctypes.c_double), _ptr(vn, ctypes.c_double))
+    return un, vn
+
+
+def euler_factor(params, u: float, v: float, phi: float) -> float:
+    """1 + dt * dR_u/du at one cell (v frozen): the Euler amplification factor."""
+    p = _params(params)
+    return float(_load().rdco_euler_factor(ctypes.byref(p), u, v, phi))
+
+
+def stimulate(u: np.ndarray, disks: Iterable[Sequence[int]], arrival: Optional[np.ndarray] = None,
+              theta: float = 0.5, step_index: int = 0) -> None:
+    """In place: u := 1.0 on every disk (cx, cy, r); v untouched."""
+    lib = _load()
+    assert u.dtype == np.float64 and u.flags.c_contiguous
+    d = [tuple(int(t) for t in x) for x in disks]
+    if not d:
+        return
+    cx = np.array([t[0] for t in d], dtype=np.int32)
+    cy = np.array([t[1] for t in d], dtype=np.int32)
+    r = np.array([t[2] for t in d], dtype=np.int32)
+    ny, nx = u.shape
+    ap = _ptr(arrival, ctypes.c_int32) if arrival is not None else None
+    lib.rdco_stimulate(nx, ny, _ptr(u, ctypes.c_double), len(d), _ptr(cx, ctypes.c_int32),
+                       _ptr(cy, ctypes.c_int32), _ptr(r, ctypes.c_int32), ap, theta, step_index)
+
+
+class Run:
+    """Oracle trajectory: state, step counter and optional trackers.
+
+    ``arrival`` (int32, NEVER where u never reached ``theta``) and ``unstable``
+    (uint8 mask of cells whose Euler factor fell below -1 in a state with index
+    >= ``unstable_from``; ``first_unstable`` is the first such index or -1)."""
+
+    def __init__(self, u0, v0, phi, params, track_arrival: bool = False, theta: float = 0.5,
+                 track_unstable: bool = False, unstable_from: int = 20):
+        self.u = _f64(u0).copy()
+        self.v = _f64(v0).copy()
+        self.phi = _f64(phi)
+        self.params = dict(params)
+        self.ny, self.nx = self.u.shape
+        self.step_index = 0
+        self.theta = float(theta)
+        self.arrival = None
+        if track_arrival:
+            self.arrival = np.full(self.u.shape, NEVER, dtype=np.int32)
+            _load().rdco_mark_arrival(self.nx, self.ny, _ptr(self.u, ctypes.c_double),
+                                      _ptr(self.arrival, ctypes.c_int32), self.theta, 0)
+        self.unstable = np.zeros(self.u.shape, dtype=np.uint8) if track_unstable else None
+        self.unstable_from = int(unstable_from)
+        self._first = ctypes.c_int64(-1)
+
+    @property
+    def first_unstable(self) -> int:
+        return int(self._first.value)
+
+    def stimulate(self, disks: Iterable[Sequence[int]]) -> None:
+        stimulate(self.u, disks, self.arrival, self.theta, self.step_index)
+
+    def advance(self, n: int) -> None:
+        if n <= 0:
+            return
+        lib = _load()
+        p = _params(self.params)
+        ap = _ptr(self.arrival, ctypes.c_int32) if self.arrival is not None else None
+        up = _ptr(self.unstable, ctypes.c_uint8) if self.unstable is not None else None
+        rc = lib.rdco_run(self.nx, self.ny, ctypes.byref(p), _ptr(self.u, ctypes.c_double),
+                          _ptr(self.v, ctypes.c_double), _ptr(self.phi, ctypes.c_double),
+                          int(n), self.step_index, ap, self.theta, up, self.unstable_from,
+                          ctypes.byref(self._first))
+        if rc != 0:
+            raise MemoryError("oracle scratch allocation failed")
+        self.step_index += int(n)
+
+    def run_schedule(self, stimuli, until: int) -> None:
+        """Advance to state index ``until``, applying each stimulus (objects
+        with .step/.cx/.cy/.r, or tuples (step, cx, cy, r)) right before the
+        step that leaves state ``step``."""
+        groups = {}
+        for s in stimuli:
+            t = (s.step, s.cx, s.cy, s.r) if hasattr(s, "step") else tuple(s)
+            groups.setdefault(int(t[0]), []).append(t[1:])
+        for when in sorted(groups):
+            if when < self.step_index or when > until:
+                continue
+            self.advance(when - self.step_index)
+            self.stimulate(groups[when])
+        self.advance(until - self.step_index)
+
+
+def run_workload(wl, steps: Optional[int] = None, **kw) -> Run:
+    """Run a generated workload (``paper_1901_06535_amd.inputs.Workload`` or
+    any object with u0, v0, phi, params, stimuli, steps) on the oracle."""
+    r = Run(wl.u0, wl.v0, wl.phi, wl.params, **kw)
+    r.run_schedule(wl.stimuli, wl.steps if steps is None else steps)
+    return r
