@@ -1,0 +1,201 @@
+"""Throughput of the MI355X Oregonator stepper on the circuit workload.
+
+One benchmark step = one whole run of the workload: a 4096x4096 FP32 grid with
+a seeded circuit phi map (16-wide excitable channels at phi=0.054 on an
+inhibitory phi=0.2 background, with diode gaps and AND T-junctions), u = v = 0
+at the start, 256 r=5 stimulus disks applied at seeded steps, and 10,000
+forward-Euler steps of Eq. (1) with T steps per launch.  Inputs are resident
+in HBM before the timed region; the state is reset on the device at the start
+of every run.
+
+Prints one JSON line: GCell-updates/s (whole job), the roofline of the
+dominant kernel (measured with HIP events on the stream it runs on) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCell-updates/s (FP32 Oregonator) + %HBM peak; surrogate speedup at <=1-cell error"
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP32_ALU_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz, unpacked
+FLOP_PER_UPDATE = 21            # canonical per-cell expression, divide counted once
+BYTES_PER_CELL_LAUNCH = 20      # read u, v, phi (12 B) + write u', v' (8 B), FP32
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1901_06535_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1901_06535_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(key: str):
+    """Per-launch HBM bytes from rocprofv3 counters, if they were taken on the
+    current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec.get(key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent
+
+
+def cpu_baseline(wl, target_s: float = 12.0):
+    """The FP64 oracle on the first steps of the same workload, all host
+    cores, ~target_s seconds of work."""
+    import oracle
+    cores = os.cpu_count() or 1
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    run = oracle.Run(wl.u0, wl.v0, wl.phi, wl.params)
+    first = [s for s in wl.stimuli if s.step == 0]
+    run.stimulate([(s.cx, s.cy, s.r) for s in first])
+    t0 = time.perf_counter()
+    run.advance(2)
+    probe = time.perf_counter() - t0
+    n = max(2, int(target_s / max(probe / 2, 1e-6)))
+    t0 = time.perf_counter()
+    run.advance(n)
+    dt = time.perf_counter() - t0
+    return {"value": wl.nx * wl.ny * n / dt / 1e9, "unit": "GCell-updates/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", cores)), "kind": "oracle",
+            "sample": "FP64 oracle, first %d of %d steps of the same %dx%d circuit workload "
+                      "(%.1f s)" % (n, wl.steps, wl.nx, wl.ny, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--run-steps", type=int, default=10000)
+    ap.add_argument("--T", type=int, default=0, help="steps per launch (0 = autotune)")
+    ap.add_argument("--rows", type=int, default=0, help="tile rows (0 = autotune)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        sys.exit("bench.py measures one GPU: this build has no multi-GPU path "
+                 "(--gpus %d requested)" % args.gpus)
+
+    import torch
+    from paper_1901_06535_amd import inputs, rdc
+
+    if not os.path.exists(rdc.LIB_PATH):
+        from paper_1901_06535_amd import build
+        build.build()
+    wl = inputs.circuit(n=args.n, seed=1002, steps=args.run_steps, ndisks=256)
+    sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
+    sim.set_phi(wl.phi)
+    dev = torch.device("cuda")
+    u0 = torch.zeros((wl.ny, wl.nx), dtype=torch.float32, device=dev)
+    v0 = torch.zeros_like(u0)
+    stream = sim.stream
+
+    def reset():
+        sim.write(u0, v0)
+
+    def one_run():
+        reset()
+        start = sim.step_index
+        sched = [(s.step + start, s.cx, s.cy, s.r) for s in wl.stimuli]
+        sim.run_schedule(sched, start + wl.steps)
+
+    # -- pick steps per launch and tile height by timing the real grid
+    def time_steps(T, rows, n):
+        sim.set_block(T)
+        sim.set_tile_rows(rows)
+        reset()
+        sim.step(2 * T)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(n)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    cands = [(args.T, args.rows)] if args.T and args.rows else [
+        (T, r) for T in ((args.T,) if args.T else (4, 6, 8))
+        for r in ((args.rows,) if args.rows else (48, 64, 80))]
+    tune = {}
+    for T, r in cands:
+        tune["T%d_r%d" % (T, r)] = time_steps(T, r, 48 * T)
+    best = min(tune, key=tune.get)
+    T, rows = (int(x) for x in best[1:].split("_r"))
+    sim.set_block(T)
+    sim.set_tile_rows(rows)
+
+    for _ in range(args.warmup):
+        one_run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        one_run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    t = e0.elapsed_time(e1) / 1e3
+    updates = wl.nx * wl.ny * wl.steps * args.steps
+    value = updates / t / 1e9
+
+    # -- dominant kernel: average launch of the T-step kernel, HIP events on its stream
+    nlaunch = 200
+    t_k = time_steps(T, rows, T * nlaunch) / nlaunch
+    cells = wl.nx * wl.ny
+    flops = FLOP_PER_UPDATE * cells * T
+    achieved_tf = flops / t_k / 1e12
+    achieved_bw = BYTES_PER_CELL_LAUNCH * cells / t_k / 1e9
+    key = "stepT_T%d_r%d_%dx%d" % (T, rows, wl.nx, wl.ny)
+    traf = load_traffic(key)
+    alu = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP32_ALU_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_ALU_PEAK_TFLOPS, 4),
+           "traffic": traf["bytes_per_launch"] if traf else None}
+    hbm_eff = {"bound": "hbm", "achieved": round(achieved_bw, 1), "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": round(achieved_bw / HBM_PEAK_GBS, 4),
+               "traffic": traf["bytes_per_launch"] if traf else None}
+    roof = alu if alu["frac"] >= hbm_eff["frac"] else hbm_eff
+    other = hbm_eff if roof is alu else alu
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GCell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "circuit_%dx%d_%dsteps" % (wl.nx, wl.ny, wl.steps),
+                   "grid": [wl.nx, wl.ny], "steps_per_run": wl.steps,
+                   "stimuli": len(wl.stimuli), "steps_per_launch": T, "tile_rows": rows,
+                   "parallelism": "single GPU"},
+        "roofline": dict(roof, kernel="k_stepT<T=%d,rows=%d>" % (T, rows),
+                         launch_ms=round(1e3 * t_k, 4),
+                         algorithmic="%d FLOP/update x %d updates; %d B/cell x %d cells"
+                                     % (FLOP_PER_UPDATE, cells * T, BYTES_PER_CELL_LAUNCH, cells)),
+        "roofline_other": other,
+        "tuning_s": {k: round(v, 5) for k, v in tune.items()},
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

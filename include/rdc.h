@@ -1,0 +1,185 @@
+/*
+ * rdc.h -- C ABI of the MI355X (gfx950) Oregonator stepper, librdc.so.
+ *
+ * The library advances the two-variable Oregonator reaction-diffusion model
+ * of Stovold, "RDCSim" (arXiv 1901.06535), Sec. 2, Eq. (1):
+ *
+ *     du/dt = (1/eps) [ u - u^2 - (f v + phi) (u - q)/(u + q) ] + D_u lap(u)
+ *     dv/dt = u - v
+ *
+ * by explicit forward Euler with time step dt and the five-node Laplacian on
+ * a square grid of spacing dx (Sec. 2), with a per-cell excitability map phi
+ * (active vs. passive / inhibitive substrate drawn by the user, Sec. 3) and
+ * catalytic stimulation that sets u := 1.0 on stimulated pixels (Sec. 2).
+ * Where the paper is silent the library takes these readings:
+ *   - edges are no-flux, cell-centred: a neighbour outside the grid takes the
+ *     value of the edge cell itself;
+ *   - both updates of one step read the old state only;
+ *   - a stimulus disk (cx, cy, r) covers the cells with
+ *     (x - cx)^2 + (y - cy)^2 <= r^2.
+ *
+ * Conventions for every call:
+ *   - Every call returns an rdc_status; nothing throws or aborts across the
+ *     ABI.  After a failure rdc_last_error(ctx) holds a message.
+ *   - Planes are row-major: ny rows of nx cells, x fastest, rows `pitch`
+ *     elements apart.  Device planes handed to rdc_create must use one pitch
+ *     that is a multiple of 64 elements, be at least pitch*ny elements long
+ *     and start on a 256-byte boundary.  Cells in columns [nx, pitch) are
+ *     padding: the library may read them but never gives them meaning.
+ *   - Element type is float (RDC_FP32) or double (RDC_FP64) for u, v, phi.
+ *   - All device work is queued on the stream given to rdc_create (a
+ *     hipStream_t passed as void*; NULL = the legacy default stream).  Calls
+ *     that take HOST pointers copy synchronously and have finished with the
+ *     pointer when they return; calls on DEVICE pointers are asynchronous on
+ *     that stream.  rdc_read is the only call that always waits for the
+ *     stream; it reports device errors and the non-finite flag.
+ *   - A context is not thread-safe.  Distinct contexts are independent.
+ */
+#ifndef RDC_H
+#define RDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rdc_ctx rdc_ctx; /* opaque, one per grid */
+
+typedef enum {
+    RDC_OK = 0,
+    RDC_E_INVAL = -1,     /* bad argument: see each call */
+    RDC_E_NOMEM = -2,     /* host or device allocation failed */
+    RDC_E_DEVICE = -3,    /* a HIP call or kernel launch failed */
+    RDC_E_NONFINITE = -4, /* a non-finite u or v was produced (sticky until rdc_write) */
+    RDC_E_STATE = -5      /* call not valid in the current state */
+} rdc_status;
+
+typedef enum { RDC_FP32 = 0, RDC_FP64 = 1 } rdc_dtype;
+typedef enum { RDC_HOST = 0, RDC_DEVICE = 1 } rdc_where;
+
+/* Model and scheme parameters of Eq. (1) and Table 1 (Sec. 2). */
+typedef struct {
+    double eps; /* time-scale ratio of u and v, > 0 (+inf turns the reaction off) */
+    double f;   /* stoichiometric coefficient, finite */
+    double q;   /* propagation scaling factor, > 0 */
+    double D_u; /* diffusion coefficient of u, >= 0 */
+    double dt;  /* forward-Euler time step, > 0 */
+    double dx;  /* grid spacing, > 0 */
+} rdc_params;
+
+/* Device planes owned by the caller and borrowed by the context for its whole
+ * lifetime: two ping-pong copies of u and of v, and phi; one pitch (elements)
+ * for all five. */
+typedef struct {
+    void *u[2];
+    void *v[2];
+    void *phi;
+    int64_t pitch;
+} rdc_buffers;
+
+/* Create a context for an nx-by-ny grid (Sec. 2: one simulated reactor).
+ * Checks the buffers (non-NULL, 256-byte aligned, pitch a multiple of 64 and
+ * >= nx) and binds the current HIP device and `hip_stream`.  Parameters start
+ * at Table 1 with phi from the caller's plane; the state is whatever the u[0]
+ * and v[0] planes hold; the step counter is 0.
+ * Errors: RDC_E_INVAL for nx or ny < 1, a bad buffer or a NULL `out`;
+ * RDC_E_NOMEM / RDC_E_DEVICE if the small device status word cannot be made. */
+rdc_status rdc_create(int32_t nx, int32_t ny, rdc_dtype dtype, const rdc_buffers *bufs,
+                      void *hip_stream, rdc_ctx **out);
+
+/* Release the context (never the caller's planes).  Waits for its stream.
+ * NULL is accepted. */
+rdc_status rdc_destroy(rdc_ctx *ctx);
+
+/* Set eps, f, q, D_u, dt, dx (Eq. (1), Table 1; Sec. 3 notes they are meant
+ * to be user-editable).  Errors, leaving the old values in place:
+ * RDC_E_INVAL for eps <= 0 or NaN, non-finite f, q <= 0, D_u < 0, dt <= 0,
+ * dx <= 0, or dt*D_u/dx^2 > 1/4 (the explicit-diffusion stability bound of
+ * the five-node scheme). */
+rdc_status rdc_set_params(rdc_ctx *ctx, const rdc_params *p);
+
+/* Copy the excitability map phi (Sec. 3: active vs. passive substrate) from
+ * `phi` (host or device, `pitch` elements per row, ctx dtype) into the
+ * context's phi plane.  Errors: RDC_E_INVAL for NULL or pitch < nx. */
+rdc_status rdc_set_phi(rdc_ctx *ctx, const void *phi, int64_t pitch, rdc_where where);
+
+/* Replace the state (u, v) by the given planes (ctx dtype, `pitch` elements
+ * per row), reset the non-finite flag, keep the step counter.  Used for
+ * initial conditions and to resume from rdc_read output.
+ * Errors: RDC_E_INVAL for NULL or pitch < nx. */
+rdc_status rdc_write(rdc_ctx *ctx, const void *u, const void *v, int64_t pitch,
+                     rdc_where where);
+
+/* Catalytic stimulation (Sec. 2): set u := 1.0 on every cell of each of the k
+ * disks (host arrays cx[k], cy[k], r[k]; cx is the column), leave v alone.
+ * Applied to the current state, between steps; cells outside the grid are
+ * skipped.  If an arrival map is set, stimulated cells that have not arrived
+ * get the current step index.  Errors: RDC_E_INVAL for k < 0, a NULL array
+ * with k > 0, r < 0, or a disk that covers no cell of the grid. */
+rdc_status rdc_stimulate(rdc_ctx *ctx, const int32_t *cx, const int32_t *cy,
+                         const int32_t *r, int32_t k);
+
+/* Advance the state by n >= 0 forward-Euler steps (Sec. 2; how many steps
+ * pass between two renders is the simulation speed, Sec. 2).  Queued
+ * asynchronously: the library launches ceil(n/T) kernels that each take up to
+ * T steps on chip (T from rdc_set_block).  Errors: RDC_E_INVAL for n < 0,
+ * RDC_E_DEVICE if a launch fails.  Faults and the non-finite flag surface at
+ * the next rdc_read. */
+rdc_status rdc_step(rdc_ctx *ctx, int64_t n);
+
+/* Snapshot (Sec. 3.1): wait for the stream, then copy the current u and v
+ * into the given planes (host or device, `pitch` elements per row; either
+ * pointer may be NULL to skip it).  Errors: RDC_E_INVAL for a bad pitch,
+ * RDC_E_DEVICE for a device error, RDC_E_NONFINITE if any step produced a
+ * non-finite value since the last rdc_write (the copy is still made). */
+rdc_status rdc_read(rdc_ctx *ctx, void *u, void *v, int64_t pitch, rdc_where where);
+
+/* Steps per launch for FP32 contexts: T in 1..8, or 0 to choose by grid size
+ * (the default).  FP64 contexts always take one step per launch.  The result
+ * does not depend on T: every variant computes each cell with the same
+ * expression and bit-identical results.  Errors: RDC_E_INVAL outside 0..8. */
+rdc_status rdc_set_block(rdc_ctx *ctx, int32_t T);
+
+/* Rows of a temporal-blocking tile: 0 (auto) or one of the supported tile
+ * heights reported by rdc_tile_rows_supported.  Errors: RDC_E_INVAL. */
+rdc_status rdc_set_tile_rows(rdc_ctx *ctx, int32_t rows);
+
+/* Non-zero if `rows` is a tile height rdc_set_tile_rows accepts. */
+int32_t rdc_tile_rows_supported(int32_t rows);
+
+/* Device addresses of the planes that hold the current u and v (zero-copy
+ * view; valid until the next rdc_step or rdc_write).  Does not wait.
+ * Errors: RDC_E_INVAL for NULL outputs. */
+rdc_status rdc_current(rdc_ctx *ctx, void **u_dev, void **v_dev);
+
+/* Attach (or, with NULL, detach) a caller-owned int32 device plane that
+ * records for each cell the first step index at which u >= theta (the
+ * wave-front arrival time); cells that have not arrived hold INT32_MAX.
+ * Attaching initialises the plane from the current state.  `pitch` must be a
+ * multiple of 64 and >= nx.  FP32 and FP64 contexts both support it.
+ * Errors: RDC_E_INVAL for a bad pitch or alignment. */
+rdc_status rdc_set_arrival(rdc_ctx *ctx, int32_t *arrival_dev, int64_t pitch, double theta);
+
+/* Number of steps taken since rdc_create.  Errors: RDC_E_INVAL for NULL. */
+rdc_status rdc_get_step(const rdc_ctx *ctx, int64_t *step);
+
+/* Message of the last failed call on ctx ("" if none); with ctx == NULL the
+ * last failure of rdc_create.  The string is owned by the library. */
+const char *rdc_last_error(const rdc_ctx *ctx);
+
+/* Device-to-device copy of `nbytes` bytes (a multiple of 16; both pointers
+ * 16-byte aligned; regions must not overlap) by a plain streaming kernel
+ * queued on `hip_stream`.  It is the measured HBM-bandwidth ceiling that the
+ * stepper kernels are compared with.  Errors: RDC_E_INVAL for bad arguments
+ * (message via rdc_last_error(NULL)), RDC_E_DEVICE if the launch fails. */
+rdc_status rdc_copy(void *dst, const void *src, int64_t nbytes, void *hip_stream);
+
+/* Short name of a status code. */
+const char *rdc_status_string(rdc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RDC_H */

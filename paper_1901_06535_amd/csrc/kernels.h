@@ -1,0 +1,64 @@
+// kernels.h -- internal launch interface between the C ABI (api.hip) and the
+// HIP kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cell.h"
+
+namespace rdc {
+
+constexpr int32_t kNever = 0x7fffffff;  // arrival value of a cell that never arrived
+
+template <typename Real>
+struct StepArgs {
+    const Real* u;      // current u plane
+    const Real* v;      // current v plane
+    const Real* phi;    // excitability plane
+    Real* u_out;        // next u plane
+    Real* v_out;        // next v plane
+    int32_t* arrival;   // optional first-arrival plane (nullptr = off)
+    int* flag;          // sticky non-finite flag (device int)
+    int64_t pitch;      // elements per row of u, v, phi
+    int64_t apitch;     // elements per row of arrival
+    int nx, ny;
+    int step0;          // state index before this launch (for arrival times)
+    Real theta;         // arrival threshold
+    Consts<Real> k;
+};
+
+// One forward-Euler step per launch, streaming (FP32 or FP64).
+hipError_t launch_step1(const StepArgs<float>& a, hipStream_t s);
+hipError_t launch_step1(const StepArgs<double>& a, hipStream_t s);
+
+// T forward-Euler steps per launch on LDS tiles of `rows` rows (FP32).
+// T in 2..8; `rows` one of tile_rows_supported().
+hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s);
+bool tile_rows_supported(int rows);
+int tile_rows_default();
+
+// Catalytic stimulation: u := 1 on up to kMaxDisks disks per launch.
+constexpr int kMaxDisks = 64;
+struct Disks {
+    int cx[kMaxDisks], cy[kMaxDisks], r[kMaxDisks];
+    int count;
+};
+hipError_t launch_stimulate(float* u, int64_t pitch, int nx, int ny, const Disks& d,
+                            int32_t* arrival, int64_t apitch, int step, hipStream_t s);
+hipError_t launch_stimulate(double* u, int64_t pitch, int nx, int ny, const Disks& d,
+                            int32_t* arrival, int64_t apitch, int step, hipStream_t s);
+
+// arrival := (u >= theta) ? step : kNever over the grid.
+hipError_t launch_arrival_init(const float* u, int64_t pitch, int nx, int ny, float theta,
+                               int32_t* arrival, int64_t apitch, int step, hipStream_t s);
+hipError_t launch_arrival_init(const double* u, int64_t pitch, int nx, int ny, double theta,
+                               int32_t* arrival, int64_t apitch, int step, hipStream_t s);
+
+// *flag := 0 (a kernel, not a memset, so the call is safe under graph capture).
+hipError_t launch_clear_flag(int* flag, hipStream_t s);
+
+// Plain device copy of n16 16-byte words (the measured bandwidth ceiling).
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
+
+}  // namespace rdc

@@ -105,6 +105,16 @@ def _rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
+def _disk_fits(active: np.ndarray, r: int) -> np.ndarray:
+    """Cells whose whole radius-r disk ((x-cx)^2 + (y-cy)^2 <= r^2) lies on
+    ``active`` cells inside the grid: where an input disk can be placed
+    without catalysing the inhibitory background."""
+    from scipy.ndimage import binary_erosion
+    yy, xx = np.mgrid[-r:r + 1, -r:r + 1]
+    foot = (xx * xx + yy * yy) <= r * r
+    return binary_erosion(active, structure=foot, border_value=0)
+
+
 def _zeros(ny: int, nx: int) -> np.ndarray:
     return np.zeros((ny, nx), dtype=np.float32)
 
@@ -199,8 +209,12 @@ def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 2
     inhibitory background (0.2), built from (tile x tile) macro-tiles, each
     holding a straight, cross, corner, diode or AND T-junction motif at a
     random rotation.  Every channel runs along a tile's centre line, so
-    channels of neighbouring tiles join.  ``ndisks`` r=5 stimulus disks sit on
-    channel cells, each applied at a uniformly random step in [0, steps)."""
+    channels of neighbouring tiles join.  ``ndisks`` r=5 input disks, at most
+    one per macro-tile, lie wholly inside excitable channels, each applied at a
+    uniformly random step in [0, steps).  (Catalysing the phi=0.2 background,
+    or re-exciting medium still refractory from an earlier wave, drives
+    forward Euler at dt=0.001 into divergence; one disk per tile keeps the
+    inputs apart.)"""
     if n % tile:
         raise ValueError("n must be a multiple of the macro-tile size")
     rng = _rng(seed)
@@ -215,11 +229,23 @@ def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 2
     lut = np.array([PHI_INHIBITORY, PHI_EXCITABLE, DIODE_PHI_GAP, and_phi_gap],
                    dtype=np.float32)
     phi = lut[lab]
-    ys, xs = np.nonzero(lab == _CH)
-    pick = rng.integers(0, ys.size, size=ndisks)
-    when = np.sort(rng.integers(0, steps, size=ndisks))
-    stim = [Stimulus(int(t), int(xs[p]), int(ys[p]), STIM_RADIUS)
-            for t, p in zip(when, pick)]
+    # One input disk per macro-tile (tiles drawn without replacement when there
+    # are more tiles than disks), at a random position wholly inside that
+    # tile's excitable channel, at a uniformly random step.
+    fits = _disk_fits(lab == _CH, STIM_RADIUS)
+    tiles = rng.permutation(nt * nt)
+    stim = []
+    for t in tiles:
+        if len(stim) == ndisks:
+            break
+        ty, tx = divmod(int(t), nt)
+        ys, xs = np.nonzero(fits[ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile])
+        if ys.size == 0:
+            continue
+        p = int(rng.integers(0, ys.size))
+        stim.append((int(rng.integers(0, steps)), int(xs[p]) + tx * tile, int(ys[p]) + ty * tile))
+    stim.sort()
+    stim = [Stimulus(t, x, y, STIM_RADIUS) for t, x, y in stim]
     wl = Workload("circuit_%d" % n, n, n, dict(PARAMS_WORKLOAD), phi,
                   _zeros(n, n), _zeros(n, n), stim, steps, seed)
     wl.extra["motif_counts"] = [int((motifs == i).sum()) for i in range(len(_MOTIFS))]
@@ -333,7 +359,7 @@ def batch_sweep(count: int = 512, seed: int = 1004, smin: int = 64, smax: int = 
     """``count`` independent simulations: each side round(smin*(smax/smin)^U),
     U ~ U[0,1) drawn independently; eps ~ U[0.02, 0.03], phi_excitable ~
     U[0.04, 0.08], background 0.2, a channel lattice scaled to the grid, and
-    1-4 r=5 disks on channel cells at t=0."""
+    1-4 r=5 disks wholly inside channels at t=0."""
     rng = _rng(seed)
     sims: List[SimSpec] = []
     ratio = smax / smin
@@ -346,7 +372,7 @@ def batch_sweep(count: int = 512, seed: int = 1004, smin: int = 64, smax: int = 
         p["eps"] = eps
         spacing = int(max(32, min(nx, ny) // 3))
         phi = lattice_circuit(nx, ny, rng, pa, spacing=spacing)
-        ys, xs = np.nonzero(phi == np.float32(pa))
+        ys, xs = np.nonzero(_disk_fits(phi == np.float32(pa), STIM_RADIUS))
         k = int(rng.integers(1, 5))
         pick = rng.integers(0, ys.size, size=k)
         stim = [Stimulus(0, int(xs[i]), int(ys[i]), STIM_RADIUS) for i in pick]

@@ -1,0 +1,327 @@
+"""Python binding of ``librdc.so`` (the C ABI of ``include/rdc.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  The functions ``rdc_*`` mirror the C calls one to one and take
+raw addresses; :class:`Sim` wraps them for torch-owned device planes (PyTorch
+provides device memory and the stream, nothing else).
+
+The library is loaded on first use.  If it has not been built, or no GPU is
+present, calls raise -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librdc.so")
+
+RDC_OK, RDC_E_INVAL, RDC_E_NOMEM, RDC_E_DEVICE, RDC_E_NONFINITE, RDC_E_STATE = 0, -1, -2, -3, -4, -5
+RDC_FP32, RDC_FP64 = 0, 1
+RDC_HOST, RDC_DEVICE = 0, 1
+NEVER = 0x7FFFFFFF
+
+# Every symbol include/rdc.h declares.
+EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_write",
+           "rdc_stimulate", "rdc_step", "rdc_read", "rdc_set_block", "rdc_set_tile_rows",
+           "rdc_tile_rows_supported", "rdc_current", "rdc_set_arrival", "rdc_get_step",
+           "rdc_last_error", "rdc_copy", "rdc_status_string")
+
+
+class rdc_params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("eps", "f", "q", "D_u", "dt", "dx")]
+
+
+class rdc_buffers(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p * 2), ("v", ctypes.c_void_p * 2),
+                ("phi", ctypes.c_void_p), ("pitch", ctypes.c_int64)]
+
+
+class RdcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_status_name(status), message))
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librdc.so (once).  Raises if it is missing: build it with
+    ``python -m paper_1901_06535_amd.build``."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("librdc.so not built (%s); run python -m paper_1901_06535_amd.build"
+                           % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "rdc_create": (i32, [i32, i32, i32, ctypes.POINTER(rdc_buffers), vp,
+                             ctypes.POINTER(vp)]),
+        "rdc_destroy": (i32, [vp]),
+        "rdc_set_params": (i32, [vp, ctypes.POINTER(rdc_params)]),
+        "rdc_set_phi": (i32, [vp, vp, i64, i32]),
+        "rdc_write": (i32, [vp, vp, vp, i64, i32]),
+        "rdc_stimulate": (i32, [vp, i32p, i32p, i32p, i32]),
+        "rdc_step": (i32, [vp, i64]),
+        "rdc_read": (i32, [vp, vp, vp, i64, i32]),
+        "rdc_set_block": (i32, [vp, i32]),
+        "rdc_set_tile_rows": (i32, [vp, i32]),
+        "rdc_tile_rows_supported": (i32, [i32]),
+        "rdc_current": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "rdc_set_arrival": (i32, [vp, vp, i64, ctypes.c_double]),
+        "rdc_get_step": (i32, [vp, ctypes.POINTER(i64)]),
+        "rdc_last_error": (ctypes.c_char_p, [vp]),
+        "rdc_copy": (i32, [vp, vp, i64, vp]),
+        "rdc_status_string": (ctypes.c_char_p, [i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _status_name(s: int) -> str:
+    return {0: "RDC_OK", -1: "RDC_E_INVAL", -2: "RDC_E_NOMEM", -3: "RDC_E_DEVICE",
+            -4: "RDC_E_NONFINITE", -5: "RDC_E_STATE"}.get(s, "RDC_E_%d" % s)
+
+
+def _check(status: int, ctx) -> None:
+    if status != RDC_OK:
+        msg = load().rdc_last_error(ctx)
+        raise RdcError(status, msg.decode() if msg else "")
+
+
+# ----------------------------------------------------------------- raw calls
+
+def rdc_create(nx: int, ny: int, dtype: int, bufs: rdc_buffers, stream: int) -> int:
+    out = ctypes.c_void_p()
+    _check(load().rdc_create(nx, ny, dtype, ctypes.byref(bufs), stream or None,
+                             ctypes.byref(out)), None)
+    return out.value
+
+
+def rdc_destroy(ctx) -> None:
+    _check(load().rdc_destroy(ctx), None)
+
+
+def rdc_set_params(ctx, p: rdc_params) -> None:
+    _check(load().rdc_set_params(ctx, ctypes.byref(p)), ctx)
+
+
+def rdc_set_phi(ctx, ptr: int, pitch: int, where: int) -> None:
+    _check(load().rdc_set_phi(ctx, ptr, pitch, where), ctx)
+
+
+def rdc_write(ctx, u_ptr: int, v_ptr: int, pitch: int, where: int) -> None:
+    _check(load().rdc_write(ctx, u_ptr, v_ptr, pitch, where), ctx)
+
+
+def rdc_stimulate(ctx, cx: Sequence[int], cy: Sequence[int], r: Sequence[int]) -> None:
+    k = len(cx)
+    arr = [np.ascontiguousarray(a, dtype=np.int32) for a in (cx, cy, r)]
+    ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for a in arr]
+    _check(load().rdc_stimulate(ctx, ptrs[0], ptrs[1], ptrs[2], k), ctx)
+
+
+def rdc_step(ctx, n: int) -> None:
+    _check(load().rdc_step(ctx, int(n)), ctx)
+
+
+def rdc_read(ctx, u_ptr, v_ptr, pitch: int, where: int) -> int:
+    """Returns the status (RDC_OK or RDC_E_NONFINITE); raises on other errors."""
+    s = load().rdc_read(ctx, u_ptr, v_ptr, pitch, where)
+    if s not in (RDC_OK, RDC_E_NONFINITE):
+        _check(s, ctx)
+    return s
+
+
+def rdc_set_block(ctx, T: int) -> None:
+    _check(load().rdc_set_block(ctx, T), ctx)
+
+
+def rdc_set_tile_rows(ctx, rows: int) -> None:
+    _check(load().rdc_set_tile_rows(ctx, rows), ctx)
+
+
+def rdc_tile_rows_supported(rows: int) -> bool:
+    return bool(load().rdc_tile_rows_supported(rows))
+
+
+def rdc_current(ctx) -> Tuple[int, int]:
+    u = ctypes.c_void_p()
+    v = ctypes.c_void_p()
+    _check(load().rdc_current(ctx, ctypes.byref(u), ctypes.byref(v)), ctx)
+    return u.value, v.value
+
+
+def rdc_set_arrival(ctx, ptr: Optional[int], pitch: int, theta: float) -> None:
+    _check(load().rdc_set_arrival(ctx, ptr, pitch, theta), ctx)
+
+
+def rdc_get_step(ctx) -> int:
+    s = ctypes.c_int64()
+    _check(load().rdc_get_step(ctx, ctypes.byref(s)), ctx)
+    return s.value
+
+
+def rdc_last_error(ctx=None) -> str:
+    m = load().rdc_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def rdc_copy(dst: int, src: int, nbytes: int, stream: int) -> None:
+    _check(load().rdc_copy(dst, src, nbytes, stream or None), None)
+
+
+# ----------------------------------------------------------------- torch-owned simulation
+
+def pitch_for(nx: int) -> int:
+    return (nx + 63) // 64 * 64
+
+
+class Sim:
+    """One simulated grid on the current GPU: u, v (ping-pong) and phi planes
+    allocated by torch with a 64-element row pitch, driven through the C ABI.
+
+    ``params``: dict with eps, f, q, D_u, dt, dx (Eq. (1), Table 1)."""
+
+    def __init__(self, nx: int, ny: int, params=None, dtype: str = "fp32", device=None,
+                 stream=None):
+        import torch
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the stepper runs only on the HIP device")
+        load()
+        self.nx, self.ny = int(nx), int(ny)
+        self.dtype = dtype
+        self.tdtype = torch.float64 if dtype == "fp64" else torch.float32
+        self.np_dtype = np.float64 if dtype == "fp64" else np.float32
+        self.device = torch.device(device if device is not None else "cuda")
+        self.pitch = pitch_for(self.nx)
+        mk = lambda: torch.zeros((self.ny, self.pitch), dtype=self.tdtype, device=self.device)
+        self.planes = [mk() for _ in range(5)]  # u0, u1, v0, v1, phi
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b = rdc_buffers()
+        b.u[0], b.u[1] = self.planes[0].data_ptr(), self.planes[1].data_ptr()
+        b.v[0], b.v[1] = self.planes[2].data_ptr(), self.planes[3].data_ptr()
+        b.phi = self.planes[4].data_ptr()
+        b.pitch = self.pitch
+        with torch.cuda.device(self.device):
+            self.ctx = rdc_create(self.nx, self.ny, RDC_FP64 if dtype == "fp64" else RDC_FP32, b,
+                                  self.stream.cuda_stream)
+        self.arrival_plane = None
+        if params is not None:
+            self.set_params(params)
+
+    # -- parameters and inputs
+    def set_params(self, params) -> None:
+        p = rdc_params(*(float(params[k]) for k in ("eps", "f", "q", "D_u", "dt", "dx")))
+        rdc_set_params(self.ctx, p)
+
+    def _host(self, a) -> np.ndarray:
+        a = np.ascontiguousarray(a, dtype=self.np_dtype)
+        if a.shape != (self.ny, self.nx):
+            raise ValueError("expected shape %s, got %s" % ((self.ny, self.nx), a.shape))
+        return a
+
+    def set_phi(self, phi) -> None:
+        if hasattr(phi, "data_ptr"):
+            t = phi.to(self.device, self.tdtype).contiguous()
+            rdc_set_phi(self.ctx, t.data_ptr(), t.shape[-1], RDC_DEVICE)
+            self._keep = t
+        else:
+            a = self._host(phi)
+            rdc_set_phi(self.ctx, a.ctypes.data, self.nx, RDC_HOST)
+
+    def write(self, u, v) -> None:
+        if hasattr(u, "data_ptr"):
+            tu = u.to(self.device, self.tdtype).contiguous()
+            tv = v.to(self.device, self.tdtype).contiguous()
+            rdc_write(self.ctx, tu.data_ptr(), tv.data_ptr(), tu.shape[-1], RDC_DEVICE)
+            self._keep = (tu, tv)
+        else:
+            a, b = self._host(u), self._host(v)
+            rdc_write(self.ctx, a.ctypes.data, b.ctypes.data, self.nx, RDC_HOST)
+
+    def stimulate(self, disks: Iterable[Sequence[int]]) -> None:
+        d = [tuple(int(t) for t in x) for x in disks]
+        if d:
+            rdc_stimulate(self.ctx, [t[0] for t in d], [t[1] for t in d], [t[2] for t in d])
+
+    # -- stepping
+    def set_block(self, T: int) -> None:
+        rdc_set_block(self.ctx, T)
+
+    def set_tile_rows(self, rows: int) -> None:
+        rdc_set_tile_rows(self.ctx, rows)
+
+    def step(self, n: int) -> None:
+        rdc_step(self.ctx, n)
+
+    def run_schedule(self, stimuli, until: int) -> None:
+        """Advance to step index ``until``, applying each stimulus ((step, cx,
+        cy, r) tuples or objects) right before the step that leaves its step
+        index -- the same schedule rule as the oracle's."""
+        groups = {}
+        for s in stimuli:
+            t = (s.step, s.cx, s.cy, s.r) if hasattr(s, "step") else tuple(s)
+            groups.setdefault(int(t[0]), []).append(t[1:])
+        now = self.step_index
+        for when in sorted(groups):
+            if when < now or when > until:
+                continue
+            self.step(when - now)
+            now = when
+            self.stimulate(groups[when])
+        self.step(until - now)
+
+    @property
+    def step_index(self) -> int:
+        return rdc_get_step(self.ctx)
+
+    # -- outputs
+    def read(self, allow_nonfinite: bool = False) -> Tuple[np.ndarray, np.ndarray]:
+        u = np.empty((self.ny, self.nx), dtype=self.np_dtype)
+        v = np.empty((self.ny, self.nx), dtype=self.np_dtype)
+        s = rdc_read(self.ctx, u.ctypes.data, v.ctypes.data, self.nx, RDC_HOST)
+        if s == RDC_E_NONFINITE and not allow_nonfinite:
+            raise RdcError(s, rdc_last_error(self.ctx))
+        return u, v
+
+    def current(self):
+        """Torch views (ny, nx) of the planes holding the current u and v."""
+        pu, pv = rdc_current(self.ctx)
+        pick = {p.data_ptr(): p for p in self.planes[:4]}
+        return pick[pu][:, : self.nx], pick[pv][:, : self.nx]
+
+    def enable_arrival(self, theta: float = 0.5) -> None:
+        t = self._torch
+        self.arrival_plane = t.empty((self.ny, self.pitch), dtype=t.int32, device=self.device)
+        rdc_set_arrival(self.ctx, self.arrival_plane.data_ptr(), self.pitch, theta)
+
+    def arrival(self) -> np.ndarray:
+        self.stream.synchronize()
+        return self.arrival_plane[:, : self.nx].cpu().numpy()
+
+    def synchronize(self) -> None:
+        self.stream.synchronize()
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            rdc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
