@@ -132,10 +132,11 @@ def main():
 
     cands = [(args.T, args.rows)] if args.T and args.rows else [
         (T, r) for T in ((args.T,) if args.T else (4, 6, 8))
-        for r in ((args.rows,) if args.rows else (48, 64, 80))]
+        for r in ((args.rows,) if args.rows else (48, 56, 64, 80))]
     tune = {}
     for T, r in cands:
-        tune["T%d_r%d" % (T, r)] = time_steps(T, r, 48 * T)
+        n_t = 48 * T
+        tune["T%d_r%d" % (T, r)] = time_steps(T, r, n_t) / n_t    # seconds per Euler step
     best = min(tune, key=tune.get)
     T, rows = (int(x) for x in best[1:].split("_r"))
     sim.set_block(T)
@@ -188,7 +189,7 @@ def main():
                          algorithmic="%d FLOP/update x %d updates; %d B/cell x %d cells"
                                      % (FLOP_PER_UPDATE, cells * T, BYTES_PER_CELL_LAUNCH, cells)),
         "roofline_other": other,
-        "tuning_s": {k: round(v, 5) for k, v in tune.items()},
+        "tuning_us_per_step": {k: round(1e6 * v, 2) for k, v in tune.items()},
         "wall_s": round(wall, 3),
     }
     if not args.no_cpu:

@@ -37,18 +37,23 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIP_FLAGS + ["-o", tmp] + sources()
+def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
+    """Compile every csrc/*.hip into one shared library at `out`.  `extra`
+    (or the RDC_EXTRA_FLAGS environment variable) adds hipcc flags, e.g. the
+    build-time tunables -DRDC_STEP1_ROWS=32."""
+    tmp = out + ".tmp%d" % os.getpid()
+    extra = list(extra) + os.environ.get("RDC_EXTRA_FLAGS", "").split()
+    cmd = [hipcc()] + HIP_FLAGS + extra + ["-o", tmp] + sources()
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
         raise RuntimeError("hipcc failed building librdc.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    out = sys.argv[1] if len(sys.argv) > 1 else LIB
+    print(build(verbose=True, out=out, extra=sys.argv[2:]))

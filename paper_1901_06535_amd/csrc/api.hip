@@ -87,6 +87,9 @@ rdc::Consts<Real> consts(const rdc_params& p) {
     k.f = static_cast<Real>(p.f);
     k.q = static_cast<Real>(p.q);
     k.dt = static_cast<Real>(p.dt);
+    k.k0 = static_cast<Real>(1.0 + c1 - 4.0 * c2);
+    k.c1f = static_cast<Real>(c1 * p.f);
+    k.omdt = static_cast<Real>(1.0 - p.dt);
     return k;
 }
 

@@ -9,37 +9,43 @@
 
 namespace rdc {
 
-// Scheme constants in the working precision.  c1 = dt/eps scales the
-// reaction bracket, c2 = dt*D_u/dx^2 scales the five-node sum; both are
-// formed once in double on the host.
+// Scheme constants in the working precision, formed once in double on the
+// host: c1 = dt/eps scales the reaction bracket, c2 = dt*D_u/dx^2 the
+// five-node sum.  The FP32 update also uses the regrouped constants
+// k0 = 1 + c1 - 4 c2, c1f = c1 f and omdt = 1 - dt.
 template <typename Real>
 struct Consts {
     Real c1, c2, f, q, dt;
+    Real k0, c1f, omdt;
 };
 
-// FP32 update.  Contraction is pinned (fmaf where written, nowhere else) so
-// the result does not depend on the surrounding code.  The quotient
-// (u - q)/(u + q) is the hardware reciprocal refined by one Newton-Raphson
-// correction of the quotient (Markstein's scheme): a residual e = n - d*r0 is
-// formed exactly by an FMA and folded back as r0 + e*y; this lands within one
-// ulp of the correctly rounded quotient for the operand range of the model.
+// FP32 update.  The forward-Euler step of Eq. (1),
+//   u' = u + c1 [u - u^2 - (f v + phi)(u - q)/(u + q)] + c2 (s - 4u),
+//   v' = v + dt (u - v),
+// regrouped to take few instructions per cell:
+//   u' = u (k0 - c1 u) + c2 s - G (u - q)/(u + q),   G = c1 f v + c1 phi,
+//   v' = dt u + (1 - dt) v.
+// c1 phi arrives precomputed (`c1phi`, one FP32 multiply of the cell's phi),
+// the quotient is the hardware reciprocal of (u + q) (about 1 ulp) times the
+// numerator.  Contraction is pinned (fmaf where written, nowhere else), so
+// every kernel that calls this gets bit-identical results.
 __device__ __forceinline__ void cell_update(float uC, float uW, float uE, float uN, float uS,
-                                            float vC, float phiC, const Consts<float>& k,
+                                            float vC, float c1phi, const Consts<float>& k,
                                             float& u_next, float& v_next) {
 #pragma clang fp contract(off)
-    const float s = (uW + uE) + (uN + uS);          // west+east first: D4-symmetric
-    const float lap = __builtin_fmaf(-4.0f, uC, s);  // five-node sum
-    const float a = __builtin_fmaf(-uC, uC, uC);     // u - u^2
-    const float g = __builtin_fmaf(k.f, vC, phiC);   // f v + phi
-    const float num = uC - k.q;
-    const float den = uC + k.q;
-    const float y = __builtin_amdgcn_rcpf(den);
-    const float r0 = num * y;
-    const float e = __builtin_fmaf(-den, r0, num);
-    const float r = __builtin_fmaf(e, y, r0);        // (u - q)/(u + q)
-    const float Ru = __builtin_fmaf(-g, r, a);       // reaction bracket
-    u_next = __builtin_fmaf(k.c2, lap, __builtin_fmaf(k.c1, Ru, uC));
-    v_next = __builtin_fmaf(k.dt, uC - vC, vC);
+    const float s = (uW + uE) + (uN + uS);                   // west+east first: D4-symmetric
+    const float t1 = __builtin_fmaf(-k.c1, uC, k.k0);        // k0 - c1 u
+    const float A = __builtin_fmaf(t1, uC, k.c2 * s);        // u (k0 - c1 u) + c2 s
+    const float G = __builtin_fmaf(k.c1f, vC, c1phi);        // c1 (f v + phi)
+    const float h = G * __builtin_amdgcn_rcpf(uC + k.q);     // G / (u + q)
+    u_next = __builtin_fmaf(-h, uC, __builtin_fmaf(h, k.q, A));  // A - h (u - q)
+    v_next = __builtin_fmaf(k.dt, uC, k.omdt * vC);
+}
+
+// c1 * phi as the FP32 update takes it (one rounding, the same in every kernel).
+__device__ __forceinline__ float scaled_phi(float phi, const Consts<float>& k) {
+#pragma clang fp contract(off)
+    return k.c1 * phi;
 }
 
 // FP64 update: one fixed order of operations with no contraction and IEEE
@@ -62,6 +68,9 @@ __device__ __forceinline__ void cell_update(double uC, double uW, double uE, dou
     u_next = (uC + k.c1 * Ru) + k.c2 * lap;
     v_next = vC + k.dt * (uC - vC);
 }
+
+// The FP64 update takes phi itself.
+__device__ __forceinline__ double scaled_phi(double phi, const Consts<double>&) { return phi; }
 
 // Index of the cell whose value a position i (possibly outside [0, n))
 // takes under the no-flux edge: the even extension mirrored about each cell
