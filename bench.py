@@ -89,10 +89,17 @@ def main():
     ap.add_argument("--T", type=int, default=0, help="steps per launch (0 = autotune)")
     ap.add_argument("--rows", type=int, default=0, help="tile rows (0 = autotune)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--workload", default="circuit", choices=("circuit", "batch", "uniform"),
+                    help="circuit: 4096^2 circuit map, 10,000 steps (default); batch: 512-grid "
+                         "sweep, 5,000 steps, batched vs per-grid; uniform: 16384^2, 2,000 steps")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU: this build has no multi-GPU path "
                  "(--gpus %d requested)" % args.gpus)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "uniform":
+        return bench_uniform(args)
 
     import torch
     from paper_1901_06535_amd import inputs, rdc
@@ -194,6 +201,166 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_batch(args):
+    """512 independent grids (sides log-uniform in [64, 1024], own eps and
+    phi_excitable, channel lattices, 1-4 disks at t=0), 5,000 steps: one
+    batched launch per T steps replayed from a HIP graph, against stepping
+    each grid through its own single-grid context."""
+    import torch
+    from paper_1901_06535_amd import inputs, rdc
+
+    if not os.path.exists(rdc.LIB_PATH):
+        from paper_1901_06535_amd import build
+        build.build()
+    sims, steps = inputs.batch_sweep(count=512, seed=1004)
+    cells = sum(s.nx * s.ny for s in sims)
+    b = rdc.BatchSim([(s.nx, s.ny, s.params) for s in sims])
+    for i, s in enumerate(sims):
+        b.set_phi(i, s.phi)
+    disks = [(i, d.cx, d.cy, d.r) for i, s in enumerate(sims) for d in s.stimuli]
+    stream = b.stream.cuda_stream
+    zeros = torch.zeros(b.pool_elems, dtype=torch.float32, device="cuda")
+    nbytes = 4 * b.pool_elems
+
+    def reset():
+        # u, v := 0 in every grid with the library's copy kernel, then the disks
+        for plane in (b.planes[0], b.planes[2]):
+            rdc.rdc_copy(plane.data_ptr(), zeros.data_ptr(), nbytes, stream)
+        b.stimulate(disks)
+
+    # autotune the batched launch on the real sweep
+    tune = {}
+    for T in (4, 6, 8):
+        for rows in (48, 56, 64):
+            b.set_block(T, rows)
+            reset()
+            b.step(2 * T)
+            e0, e1 = _events()
+            e0.record(b.stream)
+            b.step(24 * T)
+            e1.record(b.stream)
+            e1.synchronize()
+            tune["T%d_r%d" % (T, rows)] = e0.elapsed_time(e1) / 1e3 / (24 * T)
+    best = min(tune, key=tune.get)
+    T, rows = (int(x) for x in best[1:].split("_r"))
+    b.set_block(T, rows)
+    g = b.capture(steps)
+    for _ in range(args.warmup):
+        reset()
+        g.launch()
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record(b.stream)
+    for _ in range(args.steps):
+        reset()
+        g.launch()
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    value = cells * steps * args.steps / t / 1e9
+    diverged = []
+    for i in range(len(sims)):
+        try:
+            b.read(i)
+        except rdc.RdcError as e:
+            if e.status != rdc.RDC_E_NONFINITE:
+                raise
+            diverged.append(i)
+    g.close()
+    b.close()
+    del zeros
+
+    # per-grid baseline: each grid through its own context, same T and tile
+    # rows; contexts, phi and disks are set up before the timed region
+    ctxs = []
+    for s in sims:
+        sim = rdc.Sim(s.nx, s.ny, s.params, "fp32")
+        sim.set_phi(s.phi)
+        sim.set_block(T)
+        sim.set_tile_rows(rows)
+        sim.stimulate([(d.cx, d.cy, d.r) for d in s.stimuli])
+        ctxs.append(sim)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, e1 = _events()
+    e0.record()
+    for sim in ctxs:
+        sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_single = e0.elapsed_time(e1) / 1e3
+    wall_single = time.perf_counter() - t0
+    for sim in ctxs:
+        sim.close()
+    single = cells * steps / t_single / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GCell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched_sweep_512_grids_%dsteps" % steps, "grids": len(sims),
+                   "cells": cells, "steps_per_run": steps, "steps_per_launch": T,
+                   "tile_rows": rows, "graph": True, "parallelism": "single GPU"},
+        "per_grid_baseline": {"value": round(single, 2), "unit": "GCell-updates/s",
+                              "seconds": round(t_single, 3), "wall_s": round(wall_single, 3)},
+        "speedup_vs_per_grid": round(value / single, 2),
+        "diverged_grids": len(diverged),
+        "diverged_eps_max": round(max(sims[i].params["eps"] for i in diverged), 5) if diverged else None,
+        "tuning_us_per_step": {k: round(1e6 * v, 2) for k, v in tune.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_uniform(args):
+    """16384^2, phi ~ U[0.04, 0.08), 64 disks, 2,000 steps: the one-step
+    streaming kernel (HBM roofline) and the autotuned T-step kernel."""
+    import torch
+    from paper_1901_06535_amd import inputs, rdc
+
+    if not os.path.exists(rdc.LIB_PATH):
+        from paper_1901_06535_amd import build
+        build.build()
+    wl = inputs.uniform_random_phi(n=16384, seed=1003, steps=2000)
+    sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
+    sim.set_phi(wl.phi)
+    zeros = torch.zeros((wl.ny, wl.nx), dtype=torch.float32, device="cuda")
+    disks = [(s.cx, s.cy, s.r) for s in wl.stimuli]
+    res = {}
+    for T, rows in ((1, 0), (8, 48), (8, 56), (8, 64)):
+        sim.set_block(T)
+        if rows:
+            sim.set_tile_rows(rows)
+        sim.write(zeros, zeros)
+        sim.stimulate(disks)
+        sim.step(8)
+        e0, e1 = _events()
+        e0.record(sim.stream)
+        sim.step(wl.steps)
+        e1.record(sim.stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        res["T%d_r%d" % (T, rows)] = wl.nx * wl.ny * wl.steps / t / 1e9
+    best = max(res, key=res.get)
+    t1 = res["T1_r0"]
+    out = {
+        "metric": METRIC, "value": round(res[best], 2), "unit": "GCell-updates/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uniform_phi_16384x16384_2000steps", "best": best},
+        "per_variant_gcells": {k: round(v, 1) for k, v in res.items()},
+        "one_step_kernel_hbm": {"achieved_GBs": round(t1 * BYTES_PER_CELL_LAUNCH, 1),
+                                "peak_GBs": HBM_PEAK_GBS,
+                                "frac": round(t1 * BYTES_PER_CELL_LAUNCH / HBM_PEAK_GBS, 4)},
+    }
     print(json.dumps(out), flush=True)
     sim.close()
 

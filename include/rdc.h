@@ -178,6 +178,83 @@ rdc_status rdc_copy(void *dst, const void *src, int64_t nbytes, void *hip_stream
 /* Short name of a status code. */
 const char *rdc_status_string(rdc_status s);
 
+
+/* ------------------------------------------------------------------------
+ * Batched simulations: many independent grids, each with its own size,
+ * parameters and phi map (parameter sweeps and circuit variants, the paper's
+ * reproducibility aim of Sec. 1 and Sec. 5), advanced together: one launch
+ * covers every tile of every grid.  FP32 only; the per-cell update is the
+ * same as rdc_step's, so each grid evolves bit-identically to a single
+ * context with the same T.
+ * ------------------------------------------------------------------------ */
+typedef struct rdc_batch rdc_batch; /* opaque */
+typedef struct rdc_graph rdc_graph; /* opaque: a recorded sequence of launches */
+
+/* One simulation of a batch.  Its planes live inside the batch's pool
+ * planes: elements [offset, offset + pitch*ny) of each of u[0], u[1], v[0],
+ * v[1] and phi.  pitch and offset are multiples of 64 elements; the regions
+ * of different simulations must not overlap. */
+typedef struct {
+    int32_t nx, ny;
+    int64_t pitch;
+    int64_t offset;
+    rdc_params params; /* Eq. (1) parameters of this simulation (checked as in rdc_set_params) */
+} rdc_sim_desc;
+
+/* Create a batch of `count` >= 1 simulations over caller-owned FP32 pool
+ * planes of `pool_elems` elements each (pool->pitch is ignored), bound to
+ * `hip_stream`.  Copies the descriptors (host array); allocates a small
+ * device table and one status word per simulation.  The state of each
+ * simulation is whatever its region of u[0], v[0] holds.  Errors:
+ * RDC_E_INVAL for count < 1, bad sizes, pitches, offsets, overlaps,
+ * misaligned pool planes or bad parameters (message via
+ * rdc_last_error(NULL)); RDC_E_NOMEM / RDC_E_DEVICE for device setup. */
+rdc_status rdc_batch_create(int32_t count, const rdc_sim_desc *sims, const rdc_buffers *pool,
+                            int64_t pool_elems, void *hip_stream, rdc_batch **out);
+
+/* Release the batch (not the pool).  Waits for its stream.  NULL accepted. */
+rdc_status rdc_batch_destroy(rdc_batch *b);
+
+/* Steps per launch (1..8, default 8) and tile rows (48, 56 or 64, default
+ * 56) of the batched kernel.  Does not change results. */
+rdc_status rdc_batch_set_block(rdc_batch *b, int32_t T, int32_t rows);
+
+/* Copy phi of simulation `sim` (ny rows of `pitch` elements, host or
+ * device).  Errors: RDC_E_INVAL for a bad index, NULL or pitch < nx. */
+rdc_status rdc_batch_set_phi(rdc_batch *b, int32_t sim, const void *phi, int64_t pitch,
+                             rdc_where where);
+
+/* Replace the state of simulation `sim` and clear its non-finite flag. */
+rdc_status rdc_batch_write(rdc_batch *b, int32_t sim, const void *u, const void *v,
+                           int64_t pitch, rdc_where where);
+
+/* Catalytic stimulation (Sec. 2) of k disks: disk j hits simulation sim[j]
+ * (host arrays).  Errors as rdc_stimulate, plus a bad simulation index. */
+rdc_status rdc_batch_stimulate(rdc_batch *b, const int32_t *sim, const int32_t *cx,
+                               const int32_t *cy, const int32_t *r, int32_t k);
+
+/* Advance every simulation by n >= 0 steps (asynchronous, like rdc_step). */
+rdc_status rdc_batch_step(rdc_batch *b, int64_t n);
+
+/* Snapshot of simulation `sim` (waits for the stream); RDC_E_NONFINITE if
+ * that simulation produced a non-finite value since its last write. */
+rdc_status rdc_batch_read(rdc_batch *b, int32_t sim, void *u, void *v, int64_t pitch,
+                          rdc_where where);
+
+/* Record the launches of rdc_batch_step(b, n) into a HIP graph instead of
+ * running them; rdc_graph_launch then replays all of them as one submission
+ * on the batch's stream and advances the batch by n steps each time.  The
+ * recording always holds an even number of launches (one launch is split if
+ * needed), so replays keep the ping-pong planes consistent; n must be >= 2.
+ * The graph refers to the batch, which must outlive it.  Errors:
+ * RDC_E_INVAL for n < 2 or NULL; RDC_E_DEVICE if capture fails. */
+rdc_status rdc_batch_capture(rdc_batch *b, int64_t n, rdc_graph **out);
+rdc_status rdc_graph_launch(rdc_graph *g);
+rdc_status rdc_graph_destroy(rdc_graph *g);
+
+/* Message of the last failed call on b ("" if none). */
+const char *rdc_batch_last_error(const rdc_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,7 +62,7 @@ void rdco_step(int64_t nx, int64_t ny, const rdco_params *p, const double *u,
     const double c2 = p->dt * p->D_u / (p->dx * p->dx);
     const double f = p->f, q = p->q, dt = p->dt;
     int64_t y;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nx * ny >= 65536)
     for (y = 0; y < ny; ++y) {
         for (int64_t x = 0; x < nx; ++x) {
             const int64_t c = y * nx + x;
@@ -99,7 +99,7 @@ double rdco_euler_factor(const rdco_params *p, double u, double v, double phi) {
 void rdco_mark_arrival(int64_t nx, int64_t ny, const double *u, int32_t *arrival,
                        double theta, int64_t step) {
     int64_t c;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nx * ny >= 65536)
     for (c = 0; c < nx * ny; ++c)
         if (arrival[c] == RDCO_NEVER && u[c] >= theta) arrival[c] = (int32_t)step;
 }
@@ -148,7 +148,7 @@ int rdco_run(int64_t nx, int64_t ny, const rdco_params *p, double *u, double *v,
         if (unstable && state >= unstable_from) {
             int any = 0;
             int64_t c;
-#pragma omp parallel for schedule(static) reduction(| : any)
+#pragma omp parallel for schedule(static) reduction(| : any) if (n >= 65536)
             for (c = 0; c < n; ++c) {
                 if (rdco_euler_factor(p, u[c], v[c], phi[c]) < -1.0) {
                     unstable[c] = 1;

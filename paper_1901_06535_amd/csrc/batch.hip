@@ -1,0 +1,567 @@
+// batch.hip -- many independent Oregonator grids (Sec. 2, Eq. (1)) advanced
+// together: the C ABI rdc_batch_* / rdc_graph_* of include/rdc.h and its
+// kernels.
+//
+// Every grid lives in its own region of five pooled planes.  A launch covers
+// a flat list of work items (grid, tile column, tile row) built once per
+// (T, tile rows); each 512-thread workgroup takes one item, reads that grid's
+// descriptor (size, pitch, plane offset, scheme constants) and runs the same
+// tile routine as the single-grid kernel, so a grid in a batch evolves
+// bit-identically to the same grid stepped alone.  A whole run can be
+// recorded into a HIP graph and replayed as one submission.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/rdc.h"
+#include "kernels.h"
+#include "tile.h"
+
+namespace rdc {
+namespace {
+
+using namespace dev;
+
+struct SimDev {
+    int nx, ny;
+    int64_t pitch, offset;
+    Consts<float> k;
+};
+
+struct Item {
+    int sim, tx, ty, pad;
+};
+
+struct BatchArgs {
+    const float* u;
+    const float* v;
+    const float* phi;
+    float* u_out;
+    float* v_out;
+    const SimDev* sims;
+    const Item* items;
+    int* flags;
+    int nitems, per_xcd;
+};
+
+template <int T, int R>
+__global__ __launch_bounds__(kTileWaves * 64, (tile_waves_per_simd<R, false>()))
+void k_batch_stepT(BatchArgs b) {
+    __shared__ float4 lds[kTileWaves * R][64];
+    // Consecutive items are neighbouring tiles of one grid; deal them to the
+    // XCDs in contiguous runs (see k_stepT).
+    const int item = (blockIdx.x & 7) * b.per_xcd + (blockIdx.x >> 3);
+    if (item >= b.nitems) return;
+    const Item it = b.items[item];
+    const SimDev sd = b.sims[it.sim];
+    StepArgs<float> a;
+    a.u = b.u + sd.offset;
+    a.v = b.v + sd.offset;
+    a.phi = b.phi + sd.offset;
+    a.u_out = b.u_out + sd.offset;
+    a.v_out = b.v_out + sd.offset;
+    a.arrival = nullptr;
+    a.flag = b.flags + it.sim;
+    a.pitch = sd.pitch;
+    a.apitch = 0;
+    a.nx = sd.nx;
+    a.ny = sd.ny;
+    a.step0 = 0;
+    a.theta = 0.0f;
+    a.k = sd.k;
+    step_tile<T, R, false>(a, it.tx, it.ty, lds);
+}
+
+struct BatchDisks {
+    int sim[kMaxDisks], cx[kMaxDisks], cy[kMaxDisks], r[kMaxDisks];
+    int count;
+};
+
+__global__ __launch_bounds__(256) void k_batch_stimulate(float* u, const SimDev* sims,
+                                                         BatchDisks d) {
+    const int i = blockIdx.x;
+    if (i >= d.count) return;
+    const SimDev sd = sims[d.sim[i]];
+    const int64_t cx = d.cx[i], cy = d.cy[i], r = d.r[i];
+    const int64_t x_lo = cx - r > 0 ? cx - r : 0;
+    const int64_t x_hi = cx + r < sd.nx - 1 ? cx + r : sd.nx - 1;
+    const int64_t y_lo = cy - r > 0 ? cy - r : 0;
+    const int64_t y_hi = cy + r < sd.ny - 1 ? cy + r : sd.ny - 1;
+    if (x_hi < x_lo || y_hi < y_lo) return;
+    const int64_t w = x_hi - x_lo + 1, n = w * (y_hi - y_lo + 1);
+    float* base = u + sd.offset;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+        const int64_t x = x_lo + j % w, y = y_lo + j / w;
+        const int64_t dx = x - cx, dy = y - cy;
+        if (dx * dx + dy * dy <= r * r) base[y * sd.pitch + x] = 1.0f;
+    }
+}
+
+__global__ void k_clear_flags(int* flags, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        flags[i] = 0;
+}
+
+template <int T, int R>
+hipError_t batch_launch(const BatchArgs& b, hipStream_t s) {
+    const dim3 grid(8 * b.per_xcd), block(kTileWaves * 64);
+    hipLaunchKernelGGL((k_batch_stepT<T, R>), grid, block, 0, s, b);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t batch_launch_T(const BatchArgs& b, int T, hipStream_t s) {
+    switch (T) {
+        case 1: return batch_launch<1, R>(b, s);
+        case 2: return batch_launch<2, R>(b, s);
+        case 3: return batch_launch<3, R>(b, s);
+        case 4: return batch_launch<4, R>(b, s);
+        case 5: return batch_launch<5, R>(b, s);
+        case 6: return batch_launch<6, R>(b, s);
+        case 7: return batch_launch<7, R>(b, s);
+        case 8: return batch_launch<8, R>(b, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_launch_any(const BatchArgs& b, int T, int rows, hipStream_t s) {
+    switch (rows) {
+        case 48: return batch_launch_T<6>(b, T, s);
+        case 56: return batch_launch_T<7>(b, T, s);
+        case 64: return batch_launch_T<8>(b, T, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+}  // namespace rdc
+
+struct rdc_batch {
+    int count = 0;
+    std::vector<rdc_sim_desc> sims;
+    float* pool[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // u0 u1 v0 v1 phi
+    int64_t pool_elems = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int cur = 0;
+    int T = 8, rows = 56;
+    int64_t step = 0;
+    rdc::SimDev* d_sims = nullptr;
+    int* d_flags = nullptr;
+    std::map<std::pair<int, int>, std::pair<rdc::Item*, int>> items;  // (T, rows) -> list
+    std::string err;
+};
+
+struct rdc_graph {
+    rdc_batch* b = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t n = 0;
+};
+
+namespace {
+
+std::string g_batch_error;
+
+rdc_status bfail(rdc_batch* b, rdc_status s, const std::string& m) {
+    if (b)
+        b->err = m;
+    else
+        g_batch_error = m;
+    return s;
+}
+
+rdc_status bhip(rdc_batch* b, hipError_t e, const char* what) {
+    return bfail(b, RDC_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const char* check_sim_params(const rdc_params& p) {
+    if (!(p.eps > 0.0)) return "eps must be > 0";
+    if (!std::isfinite(p.f)) return "f must be finite";
+    if (!(p.q > 0.0) || !std::isfinite(p.q)) return "q must be finite and > 0";
+    if (!(p.D_u >= 0.0) || !std::isfinite(p.D_u)) return "D_u must be finite and >= 0";
+    if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return "dt must be finite and > 0";
+    if (!(p.dx > 0.0) || !std::isfinite(p.dx)) return "dx must be finite and > 0";
+    if (p.dt * p.D_u / (p.dx * p.dx) > 0.25)
+        return "dt*D_u/dx^2 exceeds 1/4, the explicit five-node diffusion bound";
+    return nullptr;
+}
+
+rdc::Consts<float> sim_consts(const rdc_params& p) {
+    // Same constants, in the same order, as the single-grid path.
+    const double c1 = p.dt / p.eps;
+    const double c2 = p.dt * p.D_u / (p.dx * p.dx);
+    rdc::Consts<float> k;
+    k.c1 = static_cast<float>(c1);
+    k.c2 = static_cast<float>(c2);
+    k.f = static_cast<float>(p.f);
+    k.q = static_cast<float>(p.q);
+    k.dt = static_cast<float>(p.dt);
+    k.k0 = static_cast<float>(1.0 + c1 - 4.0 * c2);
+    k.c1f = static_cast<float>(c1 * p.f);
+    k.omdt = static_cast<float>(1.0 - p.dt);
+    return k;
+}
+
+struct Dev {
+    int prev = -1;
+    explicit Dev(int d) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != d) (void)hipSetDevice(d);
+    }
+    ~Dev() {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Work items of every grid for (T, rows), built once and kept on the device.
+rdc_status items_for(rdc_batch* b, int T, int rows, const rdc::Item** out, int* n) {
+    const auto key = std::make_pair(T, rows);
+    auto it = b->items.find(key);
+    if (it == b->items.end()) {
+        const int HX = (T + 3) & ~3;
+        const int BX = rdc::dev::kTileCols - 2 * HX;
+        const int BY = rows - 2 * T;
+        std::vector<rdc::Item> list;
+        for (int s = 0; s < b->count; ++s) {
+            const int tx_n = (b->sims[s].nx + BX - 1) / BX;
+            const int ty_n = (b->sims[s].ny + BY - 1) / BY;
+            for (int ty = 0; ty < ty_n; ++ty)
+                for (int tx = 0; tx < tx_n; ++tx) list.push_back({s, tx, ty, 0});
+        }
+        rdc::Item* d = nullptr;
+        hipError_t e = hipMalloc(&d, sizeof(rdc::Item) * list.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(d, list.data(), sizeof(rdc::Item) * list.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (d) (void)hipFree(d);
+            return bhip(b, e, "work-item table");
+        }
+        it = b->items.emplace(key, std::make_pair(d, static_cast<int>(list.size()))).first;
+    }
+    *out = it->second.first;
+    *n = it->second.second;
+    return RDC_OK;
+}
+
+rdc::BatchArgs batch_args(const rdc_batch* b, const rdc::Item* items, int n) {
+    rdc::BatchArgs a;
+    a.u = b->pool[b->cur];
+    a.v = b->pool[2 + b->cur];
+    a.phi = b->pool[4];
+    a.u_out = b->pool[b->cur ^ 1];
+    a.v_out = b->pool[2 + (b->cur ^ 1)];
+    a.sims = b->d_sims;
+    a.items = items;
+    a.flags = b->d_flags;
+    a.nitems = n;
+    a.per_xcd = (n + 7) / 8;
+    return a;
+}
+
+// Steps per launch for advancing n steps: T-step launches and one remainder;
+// with `even`, one launch is split so the count of launches is even.
+std::vector<int> plan_launches(int64_t n, int T, bool even) {
+    std::vector<int> ks;
+    while (n > 0) {
+        const int k = n < T ? static_cast<int>(n) : T;
+        ks.push_back(k);
+        n -= k;
+    }
+    if (even && ks.size() % 2 == 1) {
+        for (size_t i = ks.size(); i-- > 0;) {
+            if (ks[i] >= 2) {
+                const int a = ks[i] / 2;
+                ks[i] -= a;
+                ks.insert(ks.begin() + i, a);
+                break;
+            }
+        }
+    }
+    return ks;
+}
+
+rdc_status run_launches(rdc_batch* b, const std::vector<int>& ks, hipStream_t s) {
+    for (const int k : ks) {
+        const rdc::Item* items = nullptr;
+        int n = 0;
+        rdc_status st = items_for(b, k, b->rows, &items, &n);
+        if (st != RDC_OK) return st;
+        hipError_t e = rdc::batch_launch_any(batch_args(b, items, n), k, b->rows, s);
+        if (e != hipSuccess) return bhip(b, e, "batched step launch");
+        b->cur ^= 1;
+    }
+    return RDC_OK;
+}
+
+rdc_status copy_sim_plane(rdc_batch* b, int sim, float* pool, const void* src, int64_t spitch,
+                          rdc_where where, bool to_pool) {
+    const rdc_sim_desc& d = b->sims[sim];
+    float* region = pool + d.offset;
+    hipMemcpyKind kind;
+    if (to_pool)
+        kind = where == RDC_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    else
+        kind = where == RDC_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    hipError_t e;
+    if (to_pool)
+        e = hipMemcpy2DAsync(region, d.pitch * 4, src, spitch * 4, d.nx * 4, d.ny, kind, b->stream);
+    else
+        e = hipMemcpy2DAsync(const_cast<void*>(src), spitch * 4, region, d.pitch * 4, d.nx * 4,
+                             d.ny, kind, b->stream);
+    if (e == hipSuccess && where == RDC_HOST) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "plane copy");
+    return RDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rdc_batch_last_error(const rdc_batch* b) {
+    return b ? b->err.c_str() : g_batch_error.c_str();
+}
+
+rdc_status rdc_batch_create(int32_t count, const rdc_sim_desc* sims, const rdc_buffers* pool,
+                            int64_t pool_elems, void* hip_stream, rdc_batch** out) {
+    g_batch_error.clear();
+    if (!out) return bfail(nullptr, RDC_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !sims || !pool) return bfail(nullptr, RDC_E_INVAL, "need count >= 1, sims, pool");
+    const void* planes[5] = {pool->u[0], pool->u[1], pool->v[0], pool->v[1], pool->phi};
+    for (const void* p : planes)
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255u))
+            return bfail(nullptr, RDC_E_INVAL, "pool planes must be non-NULL and 256-byte aligned");
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    for (int i = 0; i < count; ++i) {
+        const rdc_sim_desc& d = sims[i];
+        if (d.nx < 1 || d.ny < 1) return bfail(nullptr, RDC_E_INVAL, "grid sizes must be >= 1");
+        if (d.pitch < d.nx || d.pitch % 64 || d.offset < 0 || d.offset % 64)
+            return bfail(nullptr, RDC_E_INVAL, "pitch/offset must be multiples of 64, pitch >= nx");
+        if (d.pitch * 4 > INT32_MAX) return bfail(nullptr, RDC_E_INVAL, "row too long");
+        if (d.offset + d.pitch * d.ny > pool_elems)
+            return bfail(nullptr, RDC_E_INVAL, "a simulation extends past the pool");
+        if (const char* why = check_sim_params(d.params)) return bfail(nullptr, RDC_E_INVAL, why);
+        spans.push_back({d.offset, d.offset + d.pitch * d.ny});
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second)
+            return bfail(nullptr, RDC_E_INVAL, "simulation regions overlap");
+    rdc_batch* b = new (std::nothrow) rdc_batch;
+    if (!b) return bfail(nullptr, RDC_E_NOMEM, "host allocation failed");
+    b->count = count;
+    b->sims.assign(sims, sims + count);
+    for (int i = 0; i < 5; ++i) b->pool[i] = static_cast<float*>(const_cast<void*>(planes[i]));
+    b->pool_elems = pool_elems;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    std::vector<rdc::SimDev> host(count);
+    for (int i = 0; i < count; ++i)
+        host[i] = {sims[i].nx, sims[i].ny, sims[i].pitch, sims[i].offset, sim_consts(sims[i].params)};
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipMalloc(&b->d_sims, sizeof(rdc::SimDev) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->d_flags, sizeof(int) * count);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_sims, host.data(), sizeof(rdc::SimDev) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(rdc::k_clear_flags, dim3((count + 255) / 256), dim3(256), 0, b->stream,
+                           b->d_flags, count);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        const std::string m = std::string("device setup: ") + hipGetErrorString(e);
+        if (b->d_sims) (void)hipFree(b->d_sims);
+        if (b->d_flags) (void)hipFree(b->d_flags);
+        delete b;
+        return bfail(nullptr, e == hipErrorOutOfMemory ? RDC_E_NOMEM : RDC_E_DEVICE, m);
+    }
+    *out = b;
+    return RDC_OK;
+}
+
+rdc_status rdc_batch_destroy(rdc_batch* b) {
+    if (!b) return RDC_OK;
+    Dev g(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& kv : b->items) (void)hipFree(kv.second.first);
+    if (b->d_sims) (void)hipFree(b->d_sims);
+    if (b->d_flags) (void)hipFree(b->d_flags);
+    delete b;
+    return RDC_OK;
+}
+
+rdc_status rdc_batch_set_block(rdc_batch* b, int32_t T, int32_t rows) {
+    if (!b) return RDC_E_INVAL;
+    if (T < 1 || T > 8) return bfail(b, RDC_E_INVAL, "T must be in 1..8");
+    if (rows != 48 && rows != 56 && rows != 64) return bfail(b, RDC_E_INVAL, "rows must be 48, 56 or 64");
+    b->T = T;
+    b->rows = rows;
+    return RDC_OK;
+}
+
+rdc_status rdc_batch_set_phi(rdc_batch* b, int32_t sim, const void* phi, int64_t pitch,
+                             rdc_where where) {
+    if (!b) return RDC_E_INVAL;
+    if (sim < 0 || sim >= b->count || !phi || pitch < b->sims[sim].nx)
+        return bfail(b, RDC_E_INVAL, "bad simulation index, NULL or pitch < nx");
+    Dev g(b->device);
+    return copy_sim_plane(b, sim, b->pool[4], phi, pitch, where, true);
+}
+
+rdc_status rdc_batch_write(rdc_batch* b, int32_t sim, const void* u, const void* v,
+                           int64_t pitch, rdc_where where) {
+    if (!b) return RDC_E_INVAL;
+    if (sim < 0 || sim >= b->count || !u || !v || pitch < b->sims[sim].nx)
+        return bfail(b, RDC_E_INVAL, "bad simulation index, NULL or pitch < nx");
+    Dev g(b->device);
+    rdc_status s = copy_sim_plane(b, sim, b->pool[b->cur], u, pitch, where, true);
+    if (s == RDC_OK) s = copy_sim_plane(b, sim, b->pool[2 + b->cur], v, pitch, where, true);
+    if (s != RDC_OK) return s;
+    hipLaunchKernelGGL(rdc::k_clear_flags, dim3(1), dim3(64), 0, b->stream, b->d_flags + sim, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bhip(b, e, "flag reset");
+    return RDC_OK;
+}
+
+rdc_status rdc_batch_stimulate(rdc_batch* b, const int32_t* sim, const int32_t* cx,
+                               const int32_t* cy, const int32_t* r, int32_t k) {
+    if (!b) return RDC_E_INVAL;
+    if (k < 0) return bfail(b, RDC_E_INVAL, "k < 0");
+    if (k == 0) return RDC_OK;
+    if (!sim || !cx || !cy || !r) return bfail(b, RDC_E_INVAL, "disk arrays are NULL");
+    for (int32_t i = 0; i < k; ++i) {
+        if (sim[i] < 0 || sim[i] >= b->count) return bfail(b, RDC_E_INVAL, "bad simulation index");
+        if (r[i] < 0) return bfail(b, RDC_E_INVAL, "disk radius < 0");
+        const rdc_sim_desc& d = b->sims[sim[i]];
+        const int64_t px = std::min<int64_t>(std::max<int64_t>(cx[i], 0), d.nx - 1);
+        const int64_t py = std::min<int64_t>(std::max<int64_t>(cy[i], 0), d.ny - 1);
+        const int64_t dx = px - cx[i], dy = py - cy[i];
+        if (dx * dx + dy * dy > (int64_t)r[i] * r[i])
+            return bfail(b, RDC_E_INVAL, "a stimulus disk covers no cell of its grid");
+    }
+    Dev g(b->device);
+    for (int32_t i0 = 0; i0 < k; i0 += rdc::kMaxDisks) {
+        rdc::BatchDisks d;
+        d.count = std::min<int32_t>(k - i0, rdc::kMaxDisks);
+        for (int j = 0; j < d.count; ++j) {
+            d.sim[j] = sim[i0 + j];
+            d.cx[j] = cx[i0 + j];
+            d.cy[j] = cy[i0 + j];
+            d.r[j] = r[i0 + j];
+        }
+        hipLaunchKernelGGL(rdc::k_batch_stimulate, dim3(d.count), dim3(256), 0, b->stream,
+                           b->pool[b->cur], b->d_sims, d);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return bhip(b, e, "stimulate launch");
+    }
+    return RDC_OK;
+}
+
+rdc_status rdc_batch_step(rdc_batch* b, int64_t n) {
+    if (!b) return RDC_E_INVAL;
+    if (n < 0) return bfail(b, RDC_E_INVAL, "n < 0");
+    Dev g(b->device);
+    rdc_status s = run_launches(b, plan_launches(n, b->T, false), b->stream);
+    if (s == RDC_OK) b->step += n;
+    return s;
+}
+
+rdc_status rdc_batch_read(rdc_batch* b, int32_t sim, void* u, void* v, int64_t pitch,
+                          rdc_where where) {
+    if (!b) return RDC_E_INVAL;
+    if (sim < 0 || sim >= b->count || ((u || v) && pitch < b->sims[sim].nx))
+        return bfail(b, RDC_E_INVAL, "bad simulation index or pitch < nx");
+    Dev g(b->device);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "device error before read");
+    int flag = 0;
+    e = hipMemcpy(&flag, b->d_flags + sim, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bhip(b, e, "flag read");
+    if (u) {
+        rdc_status s = copy_sim_plane(b, sim, b->pool[b->cur], u, pitch, where, false);
+        if (s != RDC_OK) return s;
+    }
+    if (v) {
+        rdc_status s = copy_sim_plane(b, sim, b->pool[2 + b->cur], v, pitch, where, false);
+        if (s != RDC_OK) return s;
+    }
+    if (where == RDC_DEVICE) {
+        e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bhip(b, e, "read copy");
+    }
+    if (flag) return bfail(b, RDC_E_NONFINITE, "a non-finite u or v was produced");
+    return RDC_OK;
+}
+
+rdc_status rdc_batch_capture(rdc_batch* b, int64_t n, rdc_graph** out) {
+    if (!b) return RDC_E_INVAL;
+    if (!out || n < 2) return bfail(b, RDC_E_INVAL, "need an output and n >= 2");
+    *out = nullptr;
+    const std::vector<int> ks = plan_launches(n, b->T, true);
+    if (ks.size() % 2) return bfail(b, RDC_E_INVAL, "with T = 1, n must be even");
+    Dev g(b->device);
+    // Work-item tables are made before capture: nothing allocates inside it.
+    for (const int k : ks) {
+        const rdc::Item* items = nullptr;
+        int cnt = 0;
+        rdc_status s = items_for(b, k, b->rows, &items, &cnt);
+        if (s != RDC_OK) return s;
+    }
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return bhip(b, e, "capture stream");
+    rdc_graph* gr = new (std::nothrow) rdc_graph;
+    if (!gr) {
+        (void)hipStreamDestroy(cs);
+        return bfail(b, RDC_E_NOMEM, "host allocation failed");
+    }
+    const int cur0 = b->cur;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    rdc_status s = RDC_OK;
+    if (e == hipSuccess) s = run_launches(b, ks, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    b->cur = cur0;  // an even number of launches leaves the ping-pong index unchanged
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess && s == RDC_OK) e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || s != RDC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete gr;
+        return s != RDC_OK ? s : bhip(b, e, "graph capture");
+    }
+    gr->graph = graph;
+    gr->b = b;
+    gr->n = n;
+    *out = gr;
+    return RDC_OK;
+}
+
+rdc_status rdc_graph_launch(rdc_graph* g) {
+    if (!g || !g->b) return RDC_E_INVAL;
+    Dev d(g->b->device);
+    hipError_t e = hipGraphLaunch(g->exec, g->b->stream);
+    if (e != hipSuccess) return bhip(g->b, e, "graph launch");
+    g->b->step += g->n;
+    return RDC_OK;
+}
+
+rdc_status rdc_graph_destroy(rdc_graph* g) {
+    if (!g) return RDC_OK;
+    if (g->b) {
+        Dev d(g->b->device);
+        (void)hipStreamSynchronize(g->b->stream);
+    }
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return RDC_OK;
+}
+
+}  // extern "C"

@@ -41,6 +41,11 @@ PHI_EXCITABLE = 0.054
 PHI_INHIBITORY = 0.2
 CHANNEL_WIDTH = 16
 STIM_RADIUS = 5
+# Upper bound on the wave-front speed in cells per step at the workload
+# parameters (fronts move about 0.022 cells/step), and the extra distance
+# kept between input disks.  Used only to space input disks in space-time.
+FRONT_SPEED_BOUND = 0.03
+DISK_MARGIN = 40
 
 # Agladze-style diode and coincidence AND gate (Sec. 4), geometry constants.
 DIODE_PHI_GAP = 0.0975
@@ -209,12 +214,12 @@ def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 2
     inhibitory background (0.2), built from (tile x tile) macro-tiles, each
     holding a straight, cross, corner, diode or AND T-junction motif at a
     random rotation.  Every channel runs along a tile's centre line, so
-    channels of neighbouring tiles join.  ``ndisks`` r=5 input disks, at most
-    one per macro-tile, lie wholly inside excitable channels, each applied at a
-    uniformly random step in [0, steps).  (Catalysing the phi=0.2 background,
-    or re-exciting medium still refractory from an earlier wave, drives
-    forward Euler at dt=0.001 into divergence; one disk per tile keeps the
-    inputs apart.)"""
+    channels of neighbouring tiles join.  Up to ``ndisks`` r=5 input disks lie
+    wholly inside excitable channels at uniformly random steps in [0, steps),
+    spaced so that no disk lands where an earlier disk's wave can already
+    have passed (see below).  (Catalysing the phi=0.2 background, or
+    re-exciting medium still refractory from an earlier wave, drives forward
+    Euler at dt=0.001 into divergence.)"""
     if n % tile:
         raise ValueError("n must be a multiple of the macro-tile size")
     rng = _rng(seed)
@@ -229,23 +234,30 @@ def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 2
     lut = np.array([PHI_INHIBITORY, PHI_EXCITABLE, DIODE_PHI_GAP, and_phi_gap],
                    dtype=np.float32)
     phi = lut[lab]
-    # One input disk per macro-tile (tiles drawn without replacement when there
-    # are more tiles than disks), at a random position wholly inside that
-    # tile's excitable channel, at a uniformly random step.
+    # Input disks wholly inside excitable channels, placed in time order: a
+    # candidate (step t, centre x) is kept only if no earlier disk (t_j, x_j)
+    # could have sent a wave there yet, i.e. |x - x_j| >= FRONT_SPEED_BOUND *
+    # (t - t_j) + DISK_MARGIN (Euclidean distance bounds the path along the
+    # channels from below).  Catalysing medium that an earlier wave has left
+    # refractory drives forward Euler at dt = 0.001 into divergence.
     fits = _disk_fits(lab == _CH, STIM_RADIUS)
-    tiles = rng.permutation(nt * nt)
-    stim = []
-    for t in tiles:
-        if len(stim) == ndisks:
-            break
-        ty, tx = divmod(int(t), nt)
-        ys, xs = np.nonzero(fits[ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile])
-        if ys.size == 0:
-            continue
-        p = int(rng.integers(0, ys.size))
-        stim.append((int(rng.integers(0, steps)), int(xs[p]) + tx * tile, int(ys[p]) + ty * tile))
-    stim.sort()
-    stim = [Stimulus(t, x, y, STIM_RADIUS) for t, x, y in stim]
+    fy, fx = np.nonzero(fits)
+    cand_t = rng.integers(0, steps, size=8 * ndisks)
+    cand_p = rng.integers(0, fy.size, size=8 * ndisks)
+    order = np.argsort(cand_t, kind="stable")
+    kept = []
+    for c in order:
+        t, y, x = int(cand_t[c]), int(fy[cand_p[c]]), int(fx[cand_p[c]])
+        ok = True
+        for (tj, yj, xj) in kept:
+            if np.hypot(x - xj, y - yj) < FRONT_SPEED_BOUND * (t - tj) + DISK_MARGIN:
+                ok = False
+                break
+        if ok:
+            kept.append((t, y, x))
+            if len(kept) == ndisks:
+                break
+    stim = [Stimulus(t, x, y, STIM_RADIUS) for t, y, x in kept]
     wl = Workload("circuit_%d" % n, n, n, dict(PARAMS_WORKLOAD), phi,
                   _zeros(n, n), _zeros(n, n), stim, steps, seed)
     wl.extra["motif_counts"] = [int((motifs == i).sum()) for i in range(len(_MOTIFS))]
@@ -359,7 +371,7 @@ def batch_sweep(count: int = 512, seed: int = 1004, smin: int = 64, smax: int = 
     """``count`` independent simulations: each side round(smin*(smax/smin)^U),
     U ~ U[0,1) drawn independently; eps ~ U[0.02, 0.03], phi_excitable ~
     U[0.04, 0.08], background 0.2, a channel lattice scaled to the grid, and
-    1-4 r=5 disks wholly inside channels at t=0."""
+    1-4 r=5 disks wholly inside channels at t=0, DISK_MARGIN apart."""
     rng = _rng(seed)
     sims: List[SimSpec] = []
     ratio = smax / smin
@@ -374,8 +386,13 @@ def batch_sweep(count: int = 512, seed: int = 1004, smin: int = 64, smax: int = 
         phi = lattice_circuit(nx, ny, rng, pa, spacing=spacing)
         ys, xs = np.nonzero(_disk_fits(phi == np.float32(pa), STIM_RADIUS))
         k = int(rng.integers(1, 5))
-        pick = rng.integers(0, ys.size, size=k)
-        stim = [Stimulus(0, int(xs[i]), int(ys[i]), STIM_RADIUS) for i in pick]
+        pick = rng.integers(0, ys.size, size=4 * k)
+        stim = []
+        for i in pick:               # keep disks DISK_MARGIN apart (fewer if they do not fit)
+            if all(np.hypot(int(xs[i]) - d.cx, int(ys[i]) - d.cy) >= DISK_MARGIN for d in stim):
+                stim.append(Stimulus(0, int(xs[i]), int(ys[i]), STIM_RADIUS))
+                if len(stim) == k:
+                    break
         sims.append(SimSpec(nx, ny, p, phi, stim))
     return sims, steps
 

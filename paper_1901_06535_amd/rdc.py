@@ -28,7 +28,10 @@ NEVER = 0x7FFFFFFF
 EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_write",
            "rdc_stimulate", "rdc_step", "rdc_read", "rdc_set_block", "rdc_set_tile_rows",
            "rdc_tile_rows_supported", "rdc_current", "rdc_set_arrival", "rdc_get_step",
-           "rdc_last_error", "rdc_copy", "rdc_status_string")
+           "rdc_last_error", "rdc_copy", "rdc_status_string",
+           "rdc_batch_create", "rdc_batch_destroy", "rdc_batch_set_block", "rdc_batch_set_phi",
+           "rdc_batch_write", "rdc_batch_stimulate", "rdc_batch_step", "rdc_batch_read",
+           "rdc_batch_capture", "rdc_graph_launch", "rdc_graph_destroy", "rdc_batch_last_error")
 
 
 class rdc_params(ctypes.Structure):
@@ -38,6 +41,11 @@ class rdc_params(ctypes.Structure):
 class rdc_buffers(ctypes.Structure):
     _fields_ = [("u", ctypes.c_void_p * 2), ("v", ctypes.c_void_p * 2),
                 ("phi", ctypes.c_void_p), ("pitch", ctypes.c_int64)]
+
+
+class rdc_sim_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pitch", ctypes.c_int64),
+                ("offset", ctypes.c_int64), ("params", rdc_params)]
 
 
 class RdcError(RuntimeError):
@@ -80,6 +88,19 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_last_error": (ctypes.c_char_p, [vp]),
         "rdc_copy": (i32, [vp, vp, i64, vp]),
         "rdc_status_string": (ctypes.c_char_p, [i32]),
+        "rdc_batch_create": (i32, [i32, ctypes.POINTER(rdc_sim_desc), ctypes.POINTER(rdc_buffers),
+                                   i64, vp, ctypes.POINTER(vp)]),
+        "rdc_batch_destroy": (i32, [vp]),
+        "rdc_batch_set_block": (i32, [vp, i32, i32]),
+        "rdc_batch_set_phi": (i32, [vp, i32, vp, i64, i32]),
+        "rdc_batch_write": (i32, [vp, i32, vp, vp, i64, i32]),
+        "rdc_batch_stimulate": (i32, [vp, i32p, i32p, i32p, i32p, i32]),
+        "rdc_batch_step": (i32, [vp, i64]),
+        "rdc_batch_read": (i32, [vp, i32, vp, vp, i64, i32]),
+        "rdc_batch_capture": (i32, [vp, i64, ctypes.POINTER(vp)]),
+        "rdc_graph_launch": (i32, [vp]),
+        "rdc_graph_destroy": (i32, [vp]),
+        "rdc_batch_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -319,6 +340,140 @@ class Sim:
         if getattr(self, "ctx", None):
             rdc_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------- batched simulations
+
+def _bcheck(status: int, b) -> None:
+    if status != RDC_OK:
+        msg = load().rdc_batch_last_error(b)
+        raise RdcError(status, msg.decode() if msg else "")
+
+
+def _params_struct(params) -> rdc_params:
+    return rdc_params(*(float(params[k]) for k in ("eps", "f", "q", "D_u", "dt", "dx")))
+
+
+class BatchSim:
+    """Many independent FP32 grids advanced together (rdc_batch_*): each
+    spec is (nx, ny, params).  Planes are pooled in five torch tensors; each
+    grid's region starts on a 64-element boundary with a 64-element pitch."""
+
+    def __init__(self, specs, device=None, stream=None):
+        import torch
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the stepper runs only on the HIP device")
+        lib = load()
+        self.count = len(specs)
+        self.device = torch.device(device if device is not None else "cuda")
+        descs = (rdc_sim_desc * self.count)()
+        self.shapes = []
+        off = 0
+        for i, (nx, ny, params) in enumerate(specs):
+            pitch = pitch_for(int(nx))
+            descs[i].nx, descs[i].ny = int(nx), int(ny)
+            descs[i].pitch, descs[i].offset = pitch, off
+            descs[i].params = _params_struct(params)
+            self.shapes.append((int(nx), int(ny), pitch, off))
+            off += pitch * int(ny)
+        self.pool_elems = off
+        self.planes = [torch.zeros(off, dtype=torch.float32, device=self.device) for _ in range(5)]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b = rdc_buffers()
+        b.u[0], b.u[1] = self.planes[0].data_ptr(), self.planes[1].data_ptr()
+        b.v[0], b.v[1] = self.planes[2].data_ptr(), self.planes[3].data_ptr()
+        b.phi = self.planes[4].data_ptr()
+        b.pitch = 0
+        out = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _bcheck(lib.rdc_batch_create(self.count, descs, ctypes.byref(b), off,
+                                         self.stream.cuda_stream or None, ctypes.byref(out)), None)
+        self.b = out.value
+        self.step_index = 0
+
+    def _host(self, i, a):
+        nx, ny, _, _ = self.shapes[i]
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if a.shape != (ny, nx):
+            raise ValueError("expected shape %s, got %s" % ((ny, nx), a.shape))
+        return a
+
+    def set_block(self, T: int, rows: int = 56) -> None:
+        _bcheck(load().rdc_batch_set_block(self.b, T, rows), self.b)
+
+    def set_phi(self, i: int, phi) -> None:
+        a = self._host(i, phi)
+        _bcheck(load().rdc_batch_set_phi(self.b, i, a.ctypes.data, a.shape[1], RDC_HOST), self.b)
+
+    def write(self, i: int, u, v) -> None:
+        a, c = self._host(i, u), self._host(i, v)
+        _bcheck(load().rdc_batch_write(self.b, i, a.ctypes.data, c.ctypes.data, a.shape[1],
+                                       RDC_HOST), self.b)
+
+    def stimulate(self, disks) -> None:
+        """disks: iterable of (sim, cx, cy, r)."""
+        d = [tuple(int(t) for t in x) for x in disks]
+        if not d:
+            return
+        arr = [np.ascontiguousarray([t[j] for t in d], dtype=np.int32) for j in range(4)]
+        ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) for a in arr]
+        _bcheck(load().rdc_batch_stimulate(self.b, *ptrs, len(d)), self.b)
+
+    def step(self, n: int) -> None:
+        _bcheck(load().rdc_batch_step(self.b, int(n)), self.b)
+        self.step_index += int(n)
+
+    def read(self, i: int, allow_nonfinite: bool = False):
+        nx, ny, _, _ = self.shapes[i]
+        u = np.empty((ny, nx), np.float32)
+        v = np.empty((ny, nx), np.float32)
+        s = load().rdc_batch_read(self.b, i, u.ctypes.data, v.ctypes.data, nx, RDC_HOST)
+        if s == RDC_E_NONFINITE and allow_nonfinite:
+            return u, v
+        _bcheck(s, self.b)
+        return u, v
+
+    def capture(self, n: int) -> "BatchGraph":
+        out = ctypes.c_void_p()
+        _bcheck(load().rdc_batch_capture(self.b, int(n), ctypes.byref(out)), self.b)
+        return BatchGraph(self, out.value, int(n))
+
+    def synchronize(self) -> None:
+        self.stream.synchronize()
+
+    def close(self) -> None:
+        if getattr(self, "b", None):
+            load().rdc_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchGraph:
+    """A recorded rdc_batch_step(n): each launch() advances the batch by n."""
+
+    def __init__(self, batch: BatchSim, handle, n: int):
+        self.batch, self.g, self.n = batch, handle, n
+
+    def launch(self) -> None:
+        _bcheck(load().rdc_graph_launch(self.g), self.batch.b)
+        self.batch.step_index += self.n
+
+    def close(self) -> None:
+        if getattr(self, "g", None):
+            load().rdc_graph_destroy(self.g)
+            self.g = None
 
     def __del__(self):
         try:

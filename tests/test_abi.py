@@ -95,3 +95,34 @@ def test_copy_argument_checks(lib):
 def test_tile_rows_supported(lib):
     assert rdc.rdc_tile_rows_supported(80)
     assert not rdc.rdc_tile_rows_supported(81)
+
+
+def _descs(lib, sims):
+    arr = (rdc.rdc_sim_desc * len(sims))()
+    for i, (nx, ny, pitch, off) in enumerate(sims):
+        arr[i].nx, arr[i].ny, arr[i].pitch, arr[i].offset = nx, ny, pitch, off
+        arr[i].params = rdc.rdc_params(0.022, 1.4, 0.002, 1.0, 0.001, 0.25)
+    return arr
+
+
+@pytest.mark.parametrize("sims,pool,why", [
+    ([(10, 10, 64, 0), (10, 10, 64, 320)], 4096, "overlap"),
+    ([(10, 10, 64, 0)], 100, "past the pool"),
+    ([(10, 10, 60, 0)], 4096, "multiples of 64"),
+    ([(10, 10, 64, 32)], 4096, "multiples of 64"),
+    ([(0, 10, 64, 0)], 4096, "sizes")])
+def test_batch_create_rejects_bad_layouts(lib, sims, pool, why):
+    out = ctypes.c_void_p()
+    d = _descs(lib, sims)
+    s = lib.rdc_batch_create(len(sims), d, ctypes.byref(_bufs()), pool, None, ctypes.byref(out))
+    assert s == rdc.RDC_E_INVAL and out.value is None
+    assert why in lib.rdc_batch_last_error(None).decode()
+
+
+def test_batch_create_rejects_bad_params(lib):
+    out = ctypes.c_void_p()
+    d = _descs(lib, [(10, 10, 64, 0)])
+    d[0].params.dt = 0.1      # dt*D_u/dx^2 = 1.6 > 1/4
+    s = lib.rdc_batch_create(1, d, ctypes.byref(_bufs()), 4096, None, ctypes.byref(out))
+    assert s == rdc.RDC_E_INVAL
+    assert "1/4" in lib.rdc_batch_last_error(None).decode()
