@@ -252,8 +252,109 @@ rdc_status rdc_batch_capture(rdc_batch *b, int64_t n, rdc_graph **out);
 rdc_status rdc_graph_launch(rdc_graph *g);
 rdc_status rdc_graph_destroy(rdc_graph *g);
 
+/* Device addresses (inside the pool planes) of the u and v planes that hold
+ * the batch's current state (valid until the next step).  Errors:
+ * RDC_E_INVAL for NULL outputs. */
+rdc_status rdc_batch_current(rdc_batch *b, void **u_pool, void **v_pool);
+
 /* Message of the last failed call on b ("" if none). */
 const char *rdc_batch_last_error(const rdc_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Learned coarse stepper: the kernels a 3x3-convolution U-Net needs to be
+ * trained and run on the GPU next to the plain stepper (a surrogate that
+ * advances (u, v, phi) by K steps; the plain forward-Euler stepper of Sec. 2
+ * stays the judge and the fallback).  Activations are NHWC bfloat16 stored
+ * as 16-bit words, with a pixel stride `ld` (elements) so a layer can read
+ * or write a channel slice of a concatenation buffer; weights of a layer are
+ * [9][cout][cin] (tap = 3*(dy+1) + (dx+1)), bf16 for the convolution and fp32
+ * masters for training.  All calls queue work on `stream` and return at once;
+ * argument errors return RDC_E_INVAL with a message in rdc_nn_last_error().
+ * ------------------------------------------------------------------------ */
+
+/* 3x3 "same" convolution (zero padding) on the matrix cores: bf16 operands,
+ * fp32 accumulation, + bias (fp32, optional: NULL), optional ReLU, bf16
+ * output of channels [0, cout_store).  Requires w % 32 == 0, cin % 16 == 0,
+ * cout in {32, 64, 96, 128, 192, 256}, ldx % 8 == 0, ldy % 4 == 0, x and w 16-byte
+ * aligned, y 8-byte aligned. */
+rdc_status rdc_nn_conv3x3(const void *x, int32_t ldx, const void *w, const float *bias, void *y,
+                          int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
+                          int32_t cout, int32_t cout_store, int32_t relu, void *stream);
+
+/* Weights of the input-gradient convolution: wd[tap][ci][co] =
+ * bf16(w[8 - tap][co][ci]); rdc_nn_conv3x3 with them (cin <-> cout, no bias,
+ * no ReLU) on the output gradient gives the input gradient. */
+rdc_status rdc_nn_dgrad_weights(const float *w, void *wd, int32_t cout, int32_t cin, void *stream);
+
+/* Floats of scratch rdc_nn_conv3x3_wgrad needs for this shape. */
+int64_t rdc_nn_wgrad_scratch_floats(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout);
+
+/* Weight gradient grad[9][cout][cin] (fp32) = sum over pixels of
+ * dy[p][co] * x[p + tap offset][ci]; deterministic (fixed-order reduction of
+ * per-chunk partials).  Requires cin, cout % 32 == 0, w % 32 == 0. */
+rdc_status rdc_nn_conv3x3_wgrad(const void *x, int32_t ldx, const void *dy, int32_t lddy,
+                                float *scratch, float *grad, int32_t n, int32_t h, int32_t w,
+                                int32_t cin, int32_t cout, void *stream);
+
+/* gb[co] = sum over pixels of dy[p][co] (fp32). */
+rdc_status rdc_nn_bias_grad(const void *dy, int32_t lddy, int64_t pixels, int32_t cout, float *gb,
+                            void *stream);
+
+/* dst = bf16(src), n elements. */
+rdc_status rdc_nn_to_bf16(const float *src, void *dst, int64_t n, void *stream);
+
+/* ReLU adjoint in place: g[p][c] = 0 where y[p][c] <= 0. */
+rdc_status rdc_nn_relu_bwd(void *g, int32_t ldg, const void *y, int32_t ldy, int64_t pixels,
+                           int32_t c, void *stream);
+
+/* 2x2 average pooling to (ho, wo) and its adjoint (accumulate != 0 adds into gin). */
+rdc_status rdc_nn_pool2(const void *in, int32_t ldi, void *out, int32_t ldo, int32_t n, int32_t ho,
+                        int32_t wo, int32_t c, void *stream);
+rdc_status rdc_nn_pool2_bwd(const void *gout, int32_t ldo, void *gin, int32_t ldi, int32_t n,
+                            int32_t ho, int32_t wo, int32_t c, int32_t accumulate, void *stream);
+
+/* Nearest 2x upsampling to (ho, wo) and its adjoint (from (2hi, 2wi) to (hi, wi)). */
+rdc_status rdc_nn_up2(const void *in, int32_t ldi, void *out, int32_t ldo, int32_t n, int32_t ho,
+                      int32_t wo, int32_t c, void *stream);
+rdc_status rdc_nn_up2_bwd(const void *gout, int32_t ldo, void *gin, int32_t ldi, int32_t n,
+                          int32_t hi, int32_t wi, int32_t c, void *stream);
+
+/* Network input from stepper planes (fp32, row pitch `pitch`, image i at
+ * i*plane_stride): channels (su u, sv v, sp phi), zeros up to c. */
+rdc_status rdc_nn_prep(const float *u, const float *v, const float *phi, int64_t pitch,
+                       int64_t plane_stride, void *x, int32_t c, int32_t n, int32_t h, int32_t w,
+                       float su, float sv, float sp, void *stream);
+
+/* Prediction: uo = u + head[.,0]/su, vo = v + head[.,1]/sv. */
+rdc_status rdc_nn_apply(const float *u, const float *v, const void *head, int32_t ldh,
+                        int64_t pitch, int64_t plane_stride, float *uo, float *vo, int32_t n,
+                        int32_t h, int32_t w, float su, float sv, void *stream);
+
+/* Blocks of per-block loss partials rdc_nn_loss writes for `pixels` pixels. */
+int32_t rdc_nn_loss_blocks(int64_t pixels);
+
+/* Front-weighted squared error of the head against the scaled increments
+ * (su (ut - u), sv (vt - v)), weight 1 + front_w where u or ut crosses
+ * theta, mean over pixels; writes its gradient into g (channels 0, 1; the
+ * rest of ldg zero) and per-block partial sums into `partial`. */
+rdc_status rdc_nn_loss(const float *u, const float *v, const float *ut, const float *vt,
+                       int64_t pitch, int64_t plane_stride, const void *head, int32_t ldh,
+                       void *g, int32_t ldg, int32_t n, int32_t h, int32_t w, float su, float sv,
+                       float theta, float front_w, float *partial, void *stream);
+
+/* Adam step on fp32 parameters (gradient clipped to +-clip; lr_t includes
+ * the bias corrections). */
+rdc_status rdc_nn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr_t,
+                       float b1, float b2, float eps, float clip, void *stream);
+
+/* Front check between two u planes: adds to *count (device) the number of
+ * cells where one side is >= theta and no cell of the other side's 3x3
+ * neighbourhood is.  Zero means the fronts agree to within one cell. */
+rdc_status rdc_nn_front_check(const float *a, const float *b, int64_t pitch, int32_t nx, int32_t ny,
+                              float theta, uint32_t *count, void *stream);
+
+/* Message of the last failed rdc_nn_* call of this thread. */
+const char *rdc_nn_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -37,20 +37,34 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
-    """Compile every csrc/*.hip into one shared library at `out`.  `extra`
-    (or the RDC_EXTRA_FLAGS environment variable) adds hipcc flags, e.g. the
-    build-time tunables -DRDC_STEP1_ROWS=32."""
-    tmp = out + ".tmp%d" % os.getpid()
-    extra = list(extra) + os.environ.get("RDC_EXTRA_FLAGS", "").split()
-    cmd = [hipcc()] + HIP_FLAGS + extra + ["-o", tmp] + sources()
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
-        raise RuntimeError("hipcc failed building librdc.so")
-    os.replace(tmp, out)
+        raise RuntimeError("hipcc failed: %s" % " ".join(cmd[-3:]))
+
+
+def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
+    """Compile every csrc/*.hip (in parallel, one object each; no device code
+    crosses files) and link one shared library at `out`.  `extra` (or the
+    RDC_EXTRA_FLAGS environment variable) adds hipcc flags, e.g. the
+    build-time tunables -DRDC_STEP1_ROWS=32."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    extra = list(extra) + os.environ.get("RDC_EXTRA_FLAGS", "").split()
+    flags = [f for f in HIP_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="rdc_build_") as tmpd:
+        objs = [os.path.join(tmpd, os.path.basename(src) + ".o") for src in sources()]
+        cmds = [[hipcc()] + flags + extra + ["-c", src, "-o", obj]
+                for src, obj in zip(sources(), objs)]
+        workers = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+        tmp = out + ".tmp%d" % os.getpid()
+        _run([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
+        os.replace(tmp, out)
     return out
 
 

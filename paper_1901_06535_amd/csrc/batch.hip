@@ -499,6 +499,14 @@ rdc_status rdc_batch_read(rdc_batch* b, int32_t sim, void* u, void* v, int64_t p
     return RDC_OK;
 }
 
+rdc_status rdc_batch_current(rdc_batch* b, void** u_pool, void** v_pool) {
+    if (!b) return RDC_E_INVAL;
+    if (!u_pool || !v_pool) return bfail(b, RDC_E_INVAL, "NULL output");
+    *u_pool = b->pool[b->cur];
+    *v_pool = b->pool[2 + b->cur];
+    return RDC_OK;
+}
+
 rdc_status rdc_batch_capture(rdc_batch* b, int64_t n, rdc_graph** out) {
     if (!b) return RDC_E_INVAL;
     if (!out || n < 2) return bfail(b, RDC_E_INVAL, "need an output and n >= 2");

@@ -1,0 +1,594 @@
+// nn.hip -- kernels of the learned coarse stepper: a 3x3-convolution U-Net
+// that maps (u, v, phi) to (u, v) K steps ahead, trained and run on the GPU.
+//
+// Activations are NHWC bfloat16 with an explicit pixel stride (so a layer can
+// read or write a channel slice of a concatenation buffer).  The 3x3 "same"
+// convolution is an implicit GEMM on the CDNA3/4 matrix cores
+// (v_mfma_f32_32x32x16_bf16: bf16 operands, fp32 accumulation):
+//   forward  Y[p, co] = b[co] + sum_{tap, ci} W[tap, co, ci] X[p + off(tap), ci]
+//            one wave computes a 32-pixel row segment for all output channels
+//            (up to 8 accumulator blocks of 32 channels); A = weights
+//            (32 channels x 16 inputs), B = activations (16 inputs x 32 pixels);
+//   dgrad    the same kernel on the output gradient with the weights flipped
+//            in space and transposed in channels (a small weight kernel);
+//   wgrad    dW[tap, co, ci] = sum_p dY[p, co] X[p + off(tap), ci]: pixels
+//            are the reduction axis, so 16-pixel slabs are transposed through
+//            LDS into the MFMA operand layout; each workgroup reduces a chunk
+//            of pixels and a second kernel sums the chunk partials in a fixed
+//            order (deterministic).
+// Element-wise kernels: input preparation from the stepper planes, residual
+// output, 2x2 average pooling and nearest upsampling (and their adjoints),
+// ReLU adjoint, bias gradient, the front-weighted squared-error loss and its
+// gradient, Adam with fp32 master weights, and the front check used to decide
+// fallback to the plain stepper.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nn.h"
+
+namespace rdc {
+namespace nn {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float bf2f(__bf16 x) { return static_cast<float>(x); }
+__device__ __forceinline__ __bf16 f2bf(float x) { return static_cast<__bf16>(x); }
+
+__device__ __forceinline__ bf16x8 load8(const __bf16* p) {
+    return *reinterpret_cast<const bf16x8*>(p);
+}
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = f2bf(0.0f);
+    return z;
+}
+
+// ------------------------------------------------------------------ convolution
+
+// One wave: pixels x0..x0+31 of row y of image n, output channels
+// [0, 32*NB).  Grid: x = row segments / 4, y = N images; block = 4 waves,
+// each wave its own row segment.
+template <int NB, bool RELU, bool BIAS>
+__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int seg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int segs_per_row = a.W >> 5;
+    if (seg >= segs_per_row * a.H) return;
+    const int y = seg / segs_per_row;
+    const int x0 = (seg % segs_per_row) << 5;
+    const int n = blockIdx.y;
+    const int px = x0 + (lane & 31);          // this lane's pixel (B column, D column)
+    const int kq = (lane >> 5) << 3;          // this lane's 8-wide slice of the 16 K
+    const __bf16* X = a.x + (int64_t)n * a.H * a.W * a.ldx;
+    f32x16 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[b][i] = 0.0f;
+
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y + tap / 3 - 1;
+        const int xx = px + tap % 3 - 1;
+        const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        const __bf16* xp = X + ((int64_t)(in ? yy : 0) * a.W + (in ? xx : 0)) * a.ldx + kq;
+        const __bf16* wp = a.w + (int64_t)tap * a.cout * a.cin + (int64_t)(lane & 31) * a.cin + kq;
+        for (int c0 = 0; c0 < a.cin; c0 += 16) {
+            const bf16x8 bx = in ? load8(xp + c0) : zero8();
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const bf16x8 aw = load8(wp + (int64_t)b * 32 * a.cin + c0);
+                acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, bx, acc[b], 0, 0, 0);
+            }
+        }
+    }
+    // D[co, pixel]: lane holds pixel px and channels 8*(i/4) + 4*(lane/32) + i%4.
+    __bf16* Y = a.y + ((int64_t)n * a.H * a.W + (int64_t)y * a.W + px) * a.ldy;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int co = b * 32 + g * 8 + ((lane >> 5) << 2);
+            __bf16 out[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float t = acc[b][g * 4 + i];
+                if (BIAS) t += a.bias[co + i];
+                if (RELU) t = t > 0.0f ? t : 0.0f;
+                out[i] = f2bf(t);
+            }
+            if (co < a.cout_store) {
+                uint2 pk;
+                pk.x = (uint32_t)__builtin_bit_cast(uint16_t, out[0]) |
+                       ((uint32_t)__builtin_bit_cast(uint16_t, out[1]) << 16);
+                pk.y = (uint32_t)__builtin_bit_cast(uint16_t, out[2]) |
+                       ((uint32_t)__builtin_bit_cast(uint16_t, out[3]) << 16);
+                *reinterpret_cast<uint2*>(Y + co) = pk;
+            }
+        }
+    }
+}
+
+// dgrad weights: Wd[tap'][ci][co] = W[8 - tap'][co][ci] (bf16 from the fp32 master).
+__global__ void k_flip_weights(const float* __restrict__ w, __bf16* __restrict__ wd, int cout,
+                               int cin) {
+    const int64_t total = 9LL * cout * cin;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int co = j % cout;
+        const int64_t r = j / cout;
+        const int ci = r % cin;
+        const int tp = r / cin;
+        wd[j] = f2bf(w[((int64_t)(8 - tp) * cout + co) * cin + ci]);
+    }
+}
+
+// fp32 master weights -> bf16 copies used by the forward kernel.
+__global__ void k_to_bf16(const float* __restrict__ s, __bf16* __restrict__ d, int64_t n) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x)
+        d[j] = f2bf(s[j]);
+}
+
+// wgrad partials.  Block = one wave; grid.x = chunk of kChunkSegs 32-pixel row
+// segments (a flat index over n, y, x0), grid.y = tap * (cout/32) + co tile,
+// grid.z = ci tile (32).  Writes part[chunk][tap][co][ci] for its tile.
+constexpr int kChunkSegs = 16;
+
+__global__ __launch_bounds__(64) void k_conv3x3_wgrad(WgradArgs a) {
+    __shared__ __bf16 sdy[32][40];   // [co][pixel] (padded rows)
+    __shared__ __bf16 sx[32][40];    // [ci][pixel]
+    const int lane = threadIdx.x;
+    const int co_tiles = a.cout >> 5;
+    const int tap = blockIdx.y / co_tiles;
+    const int co0 = (blockIdx.y % co_tiles) << 5;
+    const int ci0 = blockIdx.z << 5;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int segs_per_row = a.W >> 5;
+    const int64_t total_segs = (int64_t)a.N * a.H * segs_per_row;
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    for (int s = 0; s < kChunkSegs; ++s) {
+        const int64_t seg = (int64_t)blockIdx.x * kChunkSegs + s;
+        if (seg >= total_segs) break;
+        const int x0 = (int)(seg % segs_per_row) << 5;
+        const int64_t row = seg / segs_per_row;        // n * H + y
+        const int y = (int)(row % a.H);
+        const int n = (int)(row / a.H);
+        // Stage dY[32 px][co0..co0+31] and X[shifted 32 px][ci0..ci0+31],
+        // transposed: lane loads 8 channels of pixel (lane & 31), half
+        // (lane >> 5) picks channels 0-7 / 8-15, then 16-23 / 24-31.
+        const int p = lane & 31;
+        const int64_t pix = ((int64_t)n * a.H + y) * a.W + x0 + p;
+        const int yy = y + dy, xx = x0 + p + dx;
+        const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        const int64_t xpix = ((int64_t)n * a.H + (in ? yy : 0)) * a.W + (in ? xx : 0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = ((lane >> 5) << 3) + h * 16;
+            const bf16x8 gy = load8(a.dy + pix * a.lddy + co0 + c);
+            const bf16x8 gx = in ? load8(a.x + xpix * a.ldx + ci0 + c) : zero8();
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sdy[c + j][p] = gy[j];
+                sx[c + j][p] = gx[j];
+            }
+        }
+        __syncthreads();
+        // K = 32 pixels = two MFMA K-steps of 16.
+#pragma unroll
+        for (int k0 = 0; k0 < 32; k0 += 16) {
+            const int kq = k0 + ((lane >> 5) << 3);
+            bf16x8 av, bv;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                av[j] = sdy[lane & 31][kq + j];
+                bv[j] = sx[lane & 31][kq + j];
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D[co][ci]: lane holds ci = lane & 31, co = 8*(i/4) + 4*(lane/32) + i%4.
+    float* out = a.part + (((int64_t)blockIdx.x * 9 + tap) * a.cout + co0) * a.cin + ci0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int co = (i >> 2) * 8 + ((lane >> 5) << 2) + (i & 3);
+        out[(int64_t)co * a.cin + (lane & 31)] = acc[i];
+    }
+}
+
+// Sum the wgrad partials over chunks in a fixed order: g[j] = sum_c part[c][j].
+__global__ void k_sum_chunks(const float* __restrict__ part, float* __restrict__ g, int chunks,
+                             int64_t n) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + j];
+        g[j] = s;
+    }
+}
+
+// Bias gradient: gb[co] = sum over pixels of dY[p, co]; one block per channel,
+// fixed-order tree reduction.
+__global__ __launch_bounds__(256) void k_bias_grad(const __bf16* __restrict__ dy, int64_t pixels,
+                                                   int ld, float* __restrict__ gb) {
+    __shared__ float red[256];
+    const int co = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t p = threadIdx.x; p < pixels; p += 256) s += bf2f(dy[p * ld + co]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gb[co] = red[0];
+}
+
+// ------------------------------------------------------------------ element-wise
+
+// dY := dY * (Y > 0) over a channel slice (pixels x c, strides ldg / ldy).
+__global__ void k_relu_bwd(__bf16* g, int ldg, const __bf16* y, int ldy, int64_t pixels, int c) {
+    const int64_t total = pixels * c;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = j / c;
+        const int ch = j % c;
+        if (!(bf2f(y[p * ldy + ch]) > 0.0f)) g[p * ldg + ch] = f2bf(0.0f);
+    }
+}
+
+// 2x2 average pool: out[n, y, x, c] = mean of in[n, 2y..2y+1, 2x..2x+1, c].
+__global__ void k_pool2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo,
+                        int c) {
+    const int64_t total = (int64_t)N * Ho * Wo * c;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int ch = j % c;
+        const int64_t q = j / c;
+        const int x = q % Wo;
+        const int64_t r = q / Wo;
+        const int y = r % Ho;
+        const int n = r / Ho;
+        const int Wi = 2 * Wo;
+        const int64_t b = ((int64_t)n * 2 * Ho + 2 * y) * Wi + 2 * x;
+        const float s = bf2f(in[b * ldi + ch]) + bf2f(in[(b + 1) * ldi + ch]) +
+                        bf2f(in[(b + Wi) * ldi + ch]) + bf2f(in[(b + Wi + 1) * ldi + ch]);
+        out[q * ldo + ch] = f2bf(0.25f * s);
+    }
+}
+
+// Adjoint of the 2x2 average pool, accumulated: gin[...] (+)= 0.25 gout.
+__global__ void k_pool2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int Ho,
+                            int Wo, int c, int accumulate) {
+    const int64_t total = (int64_t)N * Ho * Wo * c;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int ch = j % c;
+        const int64_t q = j / c;
+        const int x = q % Wo;
+        const int64_t r = q / Wo;
+        const int y = r % Ho;
+        const int n = r / Ho;
+        const int Wi = 2 * Wo;
+        const float g = 0.25f * bf2f(gout[q * ldo + ch]);
+        const int64_t b = ((int64_t)n * 2 * Ho + 2 * y) * Wi + 2 * x;
+        const int64_t idx[4] = {b, b + 1, b + Wi, b + Wi + 1};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            __bf16* d = gin + idx[k] * ldi + ch;
+            *d = f2bf(accumulate ? bf2f(*d) + g : g);
+        }
+    }
+}
+
+// Nearest 2x upsampling: out[n, y, x, c] = in[n, y/2, x/2, c].
+__global__ void k_up2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo,
+                      int c) {
+    const int64_t total = (int64_t)N * Ho * Wo * c;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int ch = j % c;
+        const int64_t q = j / c;
+        const int x = q % Wo;
+        const int64_t r = q / Wo;
+        const int y = r % Ho;
+        const int n = r / Ho;
+        const int64_t s = ((int64_t)n * (Ho / 2) + y / 2) * (Wo / 2) + x / 2;
+        out[q * ldo + ch] = in[s * ldi + ch];
+    }
+}
+
+// Adjoint of nearest 2x upsampling: gin[n, y, x, c] = sum of the 2x2 block.
+__global__ void k_up2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int Hi,
+                          int Wi, int c) {
+    const int64_t total = (int64_t)N * Hi * Wi * c;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int ch = j % c;
+        const int64_t q = j / c;
+        const int x = q % Wi;
+        const int64_t r = q / Wi;
+        const int y = r % Hi;
+        const int n = r / Hi;
+        const int Wo = 2 * Wi;
+        const int64_t b = ((int64_t)n * 2 * Hi + 2 * y) * Wo + 2 * x;
+        const float s = bf2f(gout[b * ldo + ch]) + bf2f(gout[(b + 1) * ldo + ch]) +
+                        bf2f(gout[(b + Wo) * ldo + ch]) + bf2f(gout[(b + Wo + 1) * ldo + ch]);
+        gin[q * ldi + ch] = f2bf(s);
+    }
+}
+
+// Network input from the stepper planes (fp32, row pitch `pitch`) of image n:
+// channels (u, v, phi) scaled by (su, sv, sp), the rest zero up to c.
+__global__ void k_prep(const float* u, const float* v, const float* phi, int64_t pitch,
+                       int64_t plane_stride, __bf16* x, int c, int N, int H, int W, float su,
+                       float sv, float sp) {
+    const int64_t total = (int64_t)N * H * W;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int xx = j % W;
+        const int64_t r = j / W;
+        const int yy = r % H;
+        const int n = r / H;
+        const int64_t o = n * plane_stride + (int64_t)yy * pitch + xx;
+        __bf16* d = x + j * c;
+        d[0] = f2bf(su * u[o]);
+        d[1] = f2bf(sv * v[o]);
+        d[2] = f2bf(sp * phi[o]);
+        for (int k = 3; k < c; ++k) d[k] = f2bf(0.0f);
+    }
+}
+
+// Prediction: (u, v)_out = (u, v)_in + (du, dv) / (su, sv) from the head's
+// first two channels (fp32 planes, same layout as k_prep).
+__global__ void k_apply(const float* u, const float* v, const __bf16* head, int ldh,
+                        int64_t pitch, int64_t plane_stride, float* uo, float* vo, int N, int H,
+                        int W, float su, float sv) {
+    const int64_t total = (int64_t)N * H * W;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int xx = j % W;
+        const int64_t r = j / W;
+        const int yy = r % H;
+        const int n = r / H;
+        const int64_t o = n * plane_stride + (int64_t)yy * pitch + xx;
+        uo[o] = u[o] + bf2f(head[j * ldh + 0]) / su;
+        vo[o] = v[o] + bf2f(head[j * ldh + 1]) / sv;
+    }
+}
+
+// Loss on the head (the scaled increments): per pixel
+//   w (|du_pred - du_true|^2 + |dv_pred - dv_true|^2),  w = 1 + front_w [front]
+// where du_true = su (u_target - u_in) and "front" marks cells where the input
+// or the target crosses theta.  Writes the gradient d loss / d head (bf16,
+// scaled by 1/pixels) into the first two channels of g (others zero) and
+// per-block partial sums of the loss.
+__global__ __launch_bounds__(256) void k_loss(const float* u, const float* v, const float* ut,
+                                              const float* vt, int64_t pitch,
+                                              int64_t plane_stride, const __bf16* head, int ldh,
+                                              __bf16* g, int ldg, int N, int H, int W, float su,
+                                              float sv, float theta, float front_w,
+                                              float* partial) {
+    __shared__ float red[256];
+    const int64_t total = (int64_t)N * H * W;
+    const float inv = 1.0f / (float)total;
+    float s = 0.0f;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int xx = j % W;
+        const int64_t r = j / W;
+        const int yy = r % H;
+        const int n = r / H;
+        const int64_t o = n * plane_stride + (int64_t)yy * pitch + xx;
+        const bool front = (u[o] >= theta) != (ut[o] >= theta);
+        const float w = 1.0f + (front ? front_w : 0.0f);
+        const float eu = bf2f(head[j * ldh + 0]) - su * (ut[o] - u[o]);
+        const float ev = bf2f(head[j * ldh + 1]) - sv * (vt[o] - v[o]);
+        s += w * (eu * eu + ev * ev);
+        g[j * ldg + 0] = f2bf(2.0f * w * eu * inv);
+        g[j * ldg + 1] = f2bf(2.0f * w * ev * inv);
+        for (int k = 2; k < ldg; ++k) g[j * ldg + k] = f2bf(0.0f);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w2 = 128; w2 > 0; w2 >>= 1) {
+        if (threadIdx.x < w2) red[threadIdx.x] += red[threadIdx.x + w2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] * inv;
+}
+
+// Adam on fp32 master parameters (bias-corrected step sizes passed in).
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr_t,
+                       float b1, float b2, float eps, float clip) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        float gj = g[j];
+        gj = gj > clip ? clip : (gj < -clip ? -clip : gj);
+        const float mj = b1 * m[j] + (1.0f - b1) * gj;
+        const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+        m[j] = mj;
+        v[j] = vj;
+        p[j] -= lr_t * mj / (sqrtf(vj) + eps);
+    }
+}
+
+// Front check: counts cells where a >= theta but no cell of b's 3x3
+// neighbourhood is, and vice versa (front error <= 1 cell iff 0).
+__global__ __launch_bounds__(256) void k_front_check(const float* a, const float* b,
+                                                     int64_t pitch, int nx, int ny, float theta,
+                                                     unsigned int* count) {
+    const int64_t total = (int64_t)nx * ny;
+    unsigned int bad = 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int x = j % nx, y = j / nx;
+        const bool ia = a[(int64_t)y * pitch + x] >= theta;
+        const bool ib = b[(int64_t)y * pitch + x] >= theta;
+        if (ia == ib) continue;
+        bool na = false, nb = false;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int yy = y + dy, xx = x + dx;
+                if (yy < 0 || yy >= ny || xx < 0 || xx >= nx) continue;
+                na |= a[(int64_t)yy * pitch + xx] >= theta;
+                nb |= b[(int64_t)yy * pitch + xx] >= theta;
+            }
+        if ((ia && !nb) || (ib && !na)) ++bad;
+    }
+    if (bad) atomicAdd(count, bad);
+}
+
+inline unsigned grid_for(int64_t n, int block = 256) {
+    const int64_t g = (n + block - 1) / block;
+    return (unsigned)(g < 16384 ? (g > 0 ? g : 1) : 16384);
+}
+
+template <int NB, bool RELU, bool BIAS>
+hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
+    const int segs = (a.W >> 5) * a.H;
+    const dim3 grid((segs + 3) / 4, a.N), block(256);
+    hipLaunchKernelGGL((k_conv3x3<NB, RELU, BIAS>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NB>
+hipError_t conv_nb(const ConvArgs& a, bool relu, bool bias, hipStream_t s) {
+    if (relu && bias) return conv_launch<NB, true, true>(a, s);
+    if (bias) return conv_launch<NB, false, true>(a, s);
+    if (relu) return conv_launch<NB, true, false>(a, s);
+    return conv_launch<NB, false, false>(a, s);
+}
+
+}  // namespace
+
+hipError_t conv3x3(const ConvArgs& a, bool relu, bool bias, hipStream_t s) {
+    switch (a.cout >> 5) {
+        case 1: return conv_nb<1>(a, relu, bias, s);
+        case 2: return conv_nb<2>(a, relu, bias, s);
+        case 3: return conv_nb<3>(a, relu, bias, s);
+        case 4: return conv_nb<4>(a, relu, bias, s);
+        case 6: return conv_nb<6>(a, relu, bias, s);
+        case 8: return conv_nb<8>(a, relu, bias, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t flip_weights(const float* w, __bf16* wd, int cout, int cin, hipStream_t s) {
+    hipLaunchKernelGGL(k_flip_weights, dim3(grid_for(9LL * cout * cin)), dim3(256), 0, s, w, wd,
+                       cout, cin);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float* src, __bf16* dst, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+int64_t wgrad_chunks(int N, int H, int W) {
+    const int64_t segs = (int64_t)N * H * (W >> 5);
+    return (segs + kChunkSegs - 1) / kChunkSegs;
+}
+
+hipError_t conv3x3_wgrad(const WgradArgs& a, float* grad, hipStream_t s) {
+    const int64_t chunks = wgrad_chunks(a.N, a.H, a.W);
+    const dim3 grid((unsigned)chunks, 9 * (a.cout >> 5), a.cin >> 5);
+    hipLaunchKernelGGL(k_conv3x3_wgrad, grid, dim3(64), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = 9LL * a.cout * a.cin;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(grid_for(n)), dim3(256), 0, s, a.part, grad,
+                       (int)chunks, n);
+    return hipGetLastError();
+}
+
+hipError_t bias_grad(const __bf16* dy, int64_t pixels, int ld, int cout, float* gb,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_bias_grad, dim3(cout), dim3(256), 0, s, dy, pixels, ld, gb);
+    return hipGetLastError();
+}
+
+hipError_t relu_bwd(__bf16* g, int ldg, const __bf16* y, int ldy, int64_t pixels, int c,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid_for(pixels * c)), dim3(256), 0, s, g, ldg, y, ldy,
+                       pixels, c);
+    return hipGetLastError();
+}
+
+hipError_t pool2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo, int c,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_pool2, dim3(grid_for((int64_t)N * Ho * Wo * c)), dim3(256), 0, s, in,
+                       ldi, out, ldo, N, Ho, Wo, c);
+    return hipGetLastError();
+}
+
+hipError_t pool2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int Ho, int Wo,
+                     int c, bool accumulate, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(grid_for((int64_t)N * Ho * Wo * c)), dim3(256), 0, s,
+                       gout, ldo, gin, ldi, N, Ho, Wo, c, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t up2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo, int c,
+               hipStream_t s) {
+    hipLaunchKernelGGL(k_up2, dim3(grid_for((int64_t)N * Ho * Wo * c)), dim3(256), 0, s, in, ldi,
+                       out, ldo, N, Ho, Wo, c);
+    return hipGetLastError();
+}
+
+hipError_t up2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int Hi, int Wi,
+                   int c, hipStream_t s) {
+    hipLaunchKernelGGL(k_up2_bwd, dim3(grid_for((int64_t)N * Hi * Wi * c)), dim3(256), 0, s,
+                       gout, ldo, gin, ldi, N, Hi, Wi, c);
+    return hipGetLastError();
+}
+
+hipError_t prep(const float* u, const float* v, const float* phi, int64_t pitch,
+                int64_t plane_stride, __bf16* x, int c, int N, int H, int W, float su, float sv,
+                float sp, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep, dim3(grid_for((int64_t)N * H * W)), dim3(256), 0, s, u, v, phi,
+                       pitch, plane_stride, x, c, N, H, W, su, sv, sp);
+    return hipGetLastError();
+}
+
+hipError_t apply(const float* u, const float* v, const __bf16* head, int ldh, int64_t pitch,
+                 int64_t plane_stride, float* uo, float* vo, int N, int H, int W, float su,
+                 float sv, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply, dim3(grid_for((int64_t)N * H * W)), dim3(256), 0, s, u, v, head,
+                       ldh, pitch, plane_stride, uo, vo, N, H, W, su, sv);
+    return hipGetLastError();
+}
+
+int loss_blocks(int64_t pixels) { return (int)grid_for(pixels); }
+
+hipError_t loss(const float* u, const float* v, const float* ut, const float* vt, int64_t pitch,
+                int64_t plane_stride, const __bf16* head, int ldh, __bf16* g, int ldg, int N,
+                int H, int W, float su, float sv, float theta, float front_w, float* partial,
+                hipStream_t s) {
+    const int64_t px = (int64_t)N * H * W;
+    hipLaunchKernelGGL(k_loss, dim3(loss_blocks(px)), dim3(256), 0, s, u, v, ut, vt, pitch,
+                       plane_stride, head, ldh, g, ldg, N, H, W, su, sv, theta, front_w, partial);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr_t, float b1,
+                float b2, float eps, float clip, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, s, p, g, m, v, n, lr_t, b1, b2,
+                       eps, clip);
+    return hipGetLastError();
+}
+
+hipError_t front_check(const float* a, const float* b, int64_t pitch, int nx, int ny,
+                       float theta, unsigned int* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_front_check, dim3(grid_for((int64_t)nx * ny)), dim3(256), 0, s, a, b,
+                       pitch, nx, ny, theta, count);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace rdc

@@ -1,0 +1,191 @@
+// nn_api.hip -- C ABI (include/rdc.h, rdc_nn_*) of the learned coarse
+// stepper's kernels: argument checks and launches on the caller's stream.
+#include <cstdint>
+#include <string>
+
+#include "../../include/rdc.h"
+#include "nn.h"
+
+namespace {
+
+thread_local std::string g_nn_error;
+
+rdc_status nfail(const char* m) {
+    g_nn_error = m;
+    return RDC_E_INVAL;
+}
+
+rdc_status nhip(hipError_t e) {
+    if (e == hipSuccess) return RDC_OK;
+    g_nn_error = std::string("launch: ") + hipGetErrorString(e);
+    return RDC_E_DEVICE;
+}
+
+bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool al8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char* rdc_nn_last_error(void) { return g_nn_error.c_str(); }
+
+rdc_status rdc_nn_conv3x3(const void* x, int32_t ldx, const void* w, const float* bias, void* y,
+                          int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
+                          int32_t cout, int32_t cout_store, int32_t relu, void* stream) {
+    if (!x || !w || !y) return nfail("NULL tensor");
+    if (n < 1 || h < 1 || wd < 32 || wd % 32) return nfail("need n, h >= 1 and w a multiple of 32");
+    if (cin < 16 || cin % 16 || !(cout == 32 || cout == 64 || cout == 96 || cout == 128 ||
+                                   cout == 192 || cout == 256))
+        return nfail("need cin % 16 == 0, cout in {32, 64, 96, 128, 192, 256}");
+    if (cout_store < 1 || cout_store > cout) return nfail("cout_store must be in 1..cout");
+    if (ldx < cin || ldx % 8 || ldy < ((cout_store + 3) & ~3) || ldy % 4)
+        return nfail("strides: ldx >= cin, ldx % 8 == 0, ldy >= cout_store rounded to 4, ldy % 4 == 0");
+    if (!al16(x) || !al16(w) || !al8(y)) return nfail("x, w need 16-byte and y 8-byte alignment");
+    rdc::nn::ConvArgs a;
+    a.x = static_cast<const __bf16*>(x);
+    a.w = static_cast<const __bf16*>(w);
+    a.bias = bias;
+    a.y = static_cast<__bf16*>(y);
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.N = n;
+    a.H = h;
+    a.W = wd;
+    a.cin = cin;
+    a.cout = cout;
+    a.cout_store = cout_store;
+    return nhip(rdc::nn::conv3x3(a, relu != 0, bias != nullptr, S(stream)));
+}
+
+rdc_status rdc_nn_dgrad_weights(const float* w, void* wd, int32_t cout, int32_t cin,
+                                void* stream) {
+    if (!w || !wd || cout < 1 || cin < 1) return nfail("bad dgrad weight arguments");
+    return nhip(rdc::nn::flip_weights(w, static_cast<__bf16*>(wd), cout, cin, S(stream)));
+}
+
+int64_t rdc_nn_wgrad_scratch_floats(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout) {
+    if (n < 1 || h < 1 || w < 32 || cin < 1 || cout < 1) return 0;
+    return rdc::nn::wgrad_chunks(n, h, w) * 9 * (int64_t)cout * cin;
+}
+
+rdc_status rdc_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_t lddy,
+                                float* scratch, float* grad, int32_t n, int32_t h, int32_t w,
+                                int32_t cin, int32_t cout, void* stream) {
+    if (!x || !dy || !scratch || !grad) return nfail("NULL tensor");
+    if (n < 1 || h < 1 || w < 32 || w % 32) return nfail("need w a multiple of 32");
+    if (cin < 32 || cin % 32 || cout < 32 || cout % 32) return nfail("need cin, cout % 32 == 0");
+    if (ldx < cin || ldx % 8 || lddy < cout || lddy % 8) return nfail("bad strides");
+    if (!al16(x) || !al16(dy)) return nfail("x, dy need 16-byte alignment");
+    rdc::nn::WgradArgs a;
+    a.x = static_cast<const __bf16*>(x);
+    a.dy = static_cast<const __bf16*>(dy);
+    a.part = scratch;
+    a.ldx = ldx;
+    a.lddy = lddy;
+    a.N = n;
+    a.H = h;
+    a.W = w;
+    a.cin = cin;
+    a.cout = cout;
+    return nhip(rdc::nn::conv3x3_wgrad(a, grad, S(stream)));
+}
+
+rdc_status rdc_nn_bias_grad(const void* dy, int32_t lddy, int64_t pixels, int32_t cout,
+                            float* gb, void* stream) {
+    if (!dy || !gb || pixels < 1 || cout < 1 || lddy < cout) return nfail("bad bias-grad arguments");
+    return nhip(rdc::nn::bias_grad(static_cast<const __bf16*>(dy), pixels, lddy, cout, gb,
+                                   S(stream)));
+}
+
+rdc_status rdc_nn_to_bf16(const float* src, void* dst, int64_t n, void* stream) {
+    if (!src || !dst || n < 0) return nfail("bad conversion arguments");
+    return nhip(rdc::nn::to_bf16(src, static_cast<__bf16*>(dst), n, S(stream)));
+}
+
+rdc_status rdc_nn_relu_bwd(void* g, int32_t ldg, const void* y, int32_t ldy, int64_t pixels,
+                           int32_t c, void* stream) {
+    if (!g || !y || pixels < 1 || c < 1 || ldg < c || ldy < c) return nfail("bad relu-bwd arguments");
+    return nhip(rdc::nn::relu_bwd(static_cast<__bf16*>(g), ldg, static_cast<const __bf16*>(y),
+                                  ldy, pixels, c, S(stream)));
+}
+
+rdc_status rdc_nn_pool2(const void* in, int32_t ldi, void* out, int32_t ldo, int32_t n,
+                        int32_t ho, int32_t wo, int32_t c, void* stream) {
+    if (!in || !out || n < 1 || ho < 1 || wo < 1 || c < 1 || ldi < c || ldo < c)
+        return nfail("bad pool arguments");
+    return nhip(rdc::nn::pool2(static_cast<const __bf16*>(in), ldi, static_cast<__bf16*>(out), ldo,
+                               n, ho, wo, c, S(stream)));
+}
+
+rdc_status rdc_nn_pool2_bwd(const void* gout, int32_t ldo, void* gin, int32_t ldi, int32_t n,
+                            int32_t ho, int32_t wo, int32_t c, int32_t accumulate, void* stream) {
+    if (!gout || !gin || n < 1 || ho < 1 || wo < 1 || c < 1 || ldi < c || ldo < c)
+        return nfail("bad pool-bwd arguments");
+    return nhip(rdc::nn::pool2_bwd(static_cast<const __bf16*>(gout), ldo, static_cast<__bf16*>(gin),
+                                   ldi, n, ho, wo, c, accumulate != 0, S(stream)));
+}
+
+rdc_status rdc_nn_up2(const void* in, int32_t ldi, void* out, int32_t ldo, int32_t n, int32_t ho,
+                      int32_t wo, int32_t c, void* stream) {
+    if (!in || !out || n < 1 || ho < 2 || wo < 2 || ho % 2 || wo % 2 || c < 1 || ldi < c || ldo < c)
+        return nfail("bad upsample arguments");
+    return nhip(rdc::nn::up2(static_cast<const __bf16*>(in), ldi, static_cast<__bf16*>(out), ldo, n,
+                             ho, wo, c, S(stream)));
+}
+
+rdc_status rdc_nn_up2_bwd(const void* gout, int32_t ldo, void* gin, int32_t ldi, int32_t n,
+                          int32_t hi, int32_t wi, int32_t c, void* stream) {
+    if (!gout || !gin || n < 1 || hi < 1 || wi < 1 || c < 1 || ldi < c || ldo < c)
+        return nfail("bad upsample-bwd arguments");
+    return nhip(rdc::nn::up2_bwd(static_cast<const __bf16*>(gout), ldo, static_cast<__bf16*>(gin),
+                                 ldi, n, hi, wi, c, S(stream)));
+}
+
+rdc_status rdc_nn_prep(const float* u, const float* v, const float* phi, int64_t pitch,
+                       int64_t plane_stride, void* x, int32_t c, int32_t n, int32_t h,
+                       int32_t w, float su, float sv, float sp, void* stream) {
+    if (!u || !v || !phi || !x || c < 3 || n < 1 || h < 1 || w < 1 || pitch < w)
+        return nfail("bad prep arguments");
+    return nhip(rdc::nn::prep(u, v, phi, pitch, plane_stride, static_cast<__bf16*>(x), c, n, h, w,
+                              su, sv, sp, S(stream)));
+}
+
+rdc_status rdc_nn_apply(const float* u, const float* v, const void* head, int32_t ldh,
+                        int64_t pitch, int64_t plane_stride, float* uo, float* vo, int32_t n,
+                        int32_t h, int32_t w, float su, float sv, void* stream) {
+    if (!u || !v || !head || !uo || !vo || ldh < 2 || n < 1 || h < 1 || w < 1 || pitch < w ||
+        su == 0.0f || sv == 0.0f)
+        return nfail("bad apply arguments");
+    return nhip(rdc::nn::apply(u, v, static_cast<const __bf16*>(head), ldh, pitch, plane_stride,
+                               uo, vo, n, h, w, su, sv, S(stream)));
+}
+
+int32_t rdc_nn_loss_blocks(int64_t pixels) { return pixels < 1 ? 0 : rdc::nn::loss_blocks(pixels); }
+
+rdc_status rdc_nn_loss(const float* u, const float* v, const float* ut, const float* vt,
+                       int64_t pitch, int64_t plane_stride, const void* head, int32_t ldh,
+                       void* g, int32_t ldg, int32_t n, int32_t h, int32_t w, float su, float sv,
+                       float theta, float front_w, float* partial, void* stream) {
+    if (!u || !v || !ut || !vt || !head || !g || !partial || ldh < 2 || ldg < 2 || n < 1 ||
+        h < 1 || w < 1 || pitch < w)
+        return nfail("bad loss arguments");
+    return nhip(rdc::nn::loss(u, v, ut, vt, pitch, plane_stride, static_cast<const __bf16*>(head),
+                              ldh, static_cast<__bf16*>(g), ldg, n, h, w, su, sv, theta, front_w,
+                              partial, S(stream)));
+}
+
+rdc_status rdc_nn_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr_t,
+                       float b1, float b2, float eps, float clip, void* stream) {
+    if (!p || !g || !m || !v || n < 0) return nfail("bad adam arguments");
+    return nhip(rdc::nn::adam(p, g, m, v, n, lr_t, b1, b2, eps, clip, S(stream)));
+}
+
+rdc_status rdc_nn_front_check(const float* a, const float* b, int64_t pitch, int32_t nx,
+                              int32_t ny, float theta, uint32_t* count, void* stream) {
+    if (!a || !b || !count || nx < 1 || ny < 1 || pitch < nx) return nfail("bad front-check arguments");
+    return nhip(rdc::nn::front_check(a, b, pitch, nx, ny, theta, count, S(stream)));
+}
+
+}  // extern "C"

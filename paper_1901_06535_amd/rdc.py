@@ -31,7 +31,13 @@ EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_wr
            "rdc_last_error", "rdc_copy", "rdc_status_string",
            "rdc_batch_create", "rdc_batch_destroy", "rdc_batch_set_block", "rdc_batch_set_phi",
            "rdc_batch_write", "rdc_batch_stimulate", "rdc_batch_step", "rdc_batch_read",
-           "rdc_batch_capture", "rdc_graph_launch", "rdc_graph_destroy", "rdc_batch_last_error")
+           "rdc_batch_capture", "rdc_graph_launch", "rdc_graph_destroy", "rdc_batch_last_error",
+           "rdc_batch_current",
+           "rdc_nn_conv3x3", "rdc_nn_dgrad_weights", "rdc_nn_wgrad_scratch_floats",
+           "rdc_nn_conv3x3_wgrad", "rdc_nn_bias_grad", "rdc_nn_to_bf16", "rdc_nn_relu_bwd",
+           "rdc_nn_pool2", "rdc_nn_pool2_bwd", "rdc_nn_up2", "rdc_nn_up2_bwd", "rdc_nn_prep",
+           "rdc_nn_apply", "rdc_nn_loss_blocks", "rdc_nn_loss", "rdc_nn_adam",
+           "rdc_nn_front_check", "rdc_nn_last_error")
 
 
 class rdc_params(ctypes.Structure):
@@ -101,6 +107,30 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_graph_launch": (i32, [vp]),
         "rdc_graph_destroy": (i32, [vp]),
         "rdc_batch_last_error": (ctypes.c_char_p, [vp]),
+        "rdc_batch_current": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "rdc_nn_conv3x3": (i32, [vp, i32, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, vp]),
+        "rdc_nn_dgrad_weights": (i32, [vp, vp, i32, i32, vp]),
+        "rdc_nn_wgrad_scratch_floats": (i64, [i32, i32, i32, i32, i32]),
+        "rdc_nn_conv3x3_wgrad": (i32, [vp, i32, vp, i32, vp, vp, i32, i32, i32, i32, i32, vp]),
+        "rdc_nn_bias_grad": (i32, [vp, i32, i64, i32, vp, vp]),
+        "rdc_nn_to_bf16": (i32, [vp, vp, i64, vp]),
+        "rdc_nn_relu_bwd": (i32, [vp, i32, vp, i32, i64, i32, vp]),
+        "rdc_nn_pool2": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, vp]),
+        "rdc_nn_pool2_bwd": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, i32, vp]),
+        "rdc_nn_up2": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, vp]),
+        "rdc_nn_up2_bwd": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, vp]),
+        "rdc_nn_prep": (i32, [vp, vp, vp, i64, i64, vp, i32, i32, i32, i32, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, vp]),
+        "rdc_nn_apply": (i32, [vp, vp, vp, i32, i64, i64, vp, vp, i32, i32, i32, ctypes.c_float,
+                               ctypes.c_float, vp]),
+        "rdc_nn_loss_blocks": (i32, [i64]),
+        "rdc_nn_loss": (i32, [vp, vp, vp, vp, i64, i64, vp, i32, vp, i32, i32, i32, i32,
+                              ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp,
+                              vp]),
+        "rdc_nn_adam": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, vp]),
+        "rdc_nn_front_check": (i32, [vp, vp, i64, i32, i32, ctypes.c_float, vp, vp]),
+        "rdc_nn_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -440,6 +470,14 @@ class BatchSim:
         _bcheck(s, self.b)
         return u, v
 
+    def current(self):
+        """Flat torch views (pool_elems,) of the pool planes holding u and v."""
+        u = ctypes.c_void_p()
+        v = ctypes.c_void_p()
+        _bcheck(load().rdc_batch_current(self.b, ctypes.byref(u), ctypes.byref(v)), self.b)
+        pick = {p.data_ptr(): p for p in self.planes[:4]}
+        return pick[u.value], pick[v.value]
+
     def capture(self, n: int) -> "BatchGraph":
         out = ctypes.c_void_p()
         _bcheck(load().rdc_batch_capture(self.b, int(n), ctypes.byref(out)), self.b)
@@ -480,3 +518,15 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- network kernels
+
+def nn(name: str, *args):
+    """Call rdc_nn_<name>(*args); raise RdcError with the library's message
+    on failure.  Tensor arguments are passed as device addresses (ints)."""
+    fn = getattr(load(), "rdc_nn_" + name)
+    st = fn(*args)
+    if st != RDC_OK:
+        msg = load().rdc_nn_last_error()
+        raise RdcError(st, msg.decode() if msg else "")
