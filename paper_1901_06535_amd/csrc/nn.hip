@@ -135,7 +135,7 @@ __global__ void k_to_bf16(const float* __restrict__ s, __bf16* __restrict__ d, i
 // wgrad partials.  Block = one wave; grid.x = chunk of kChunkSegs 32-pixel row
 // segments (a flat index over n, y, x0), grid.y = tap * (cout/32) + co tile,
 // grid.z = ci tile (32).  Writes part[chunk][tap][co][ci] for its tile.
-constexpr int kChunkSegs = 16;
+constexpr int kChunkSegs = 64;
 
 __global__ __launch_bounds__(64) void k_conv3x3_wgrad(WgradArgs a) {
     __shared__ __bf16 sdy[32][40];   // [co][pixel] (padded rows)

@@ -1,0 +1,385 @@
+"""Learned coarse stepper: a 3x3-convolution U-Net that advances the
+Oregonator state by K plain steps at once, trained and run on the GPU with
+the library's own kernels (rdc_nn_*), with the plain forward-Euler stepper of
+Sec. 2 (Eq. (1)) as data source, judge and fallback.
+
+Network (4 levels, 32-64-128-128 channels, NHWC bf16 activations, fp32
+accumulation and fp32 master weights):
+
+    x0 = (su u, sv v, sp phi, 0...)            32 ch
+    e0 = conv(conv(x0))                        32      H
+    e1 = conv(conv(pool(e0)))                  64      H/2
+    e2 = conv(conv(pool(e1)))                  128     H/4
+    b3 = conv(conv(pool(e2)))                  128     H/8
+    d2 = conv(conv([up(b3), e2]))              128     H/4
+    d1 = conv(conv([up(d2), e1]))              64      H/2
+    d0 = conv(conv([up(d1), e0]))              32      H
+    head = conv(d0) (no ReLU; channels 0, 1 used)
+    (u, v)_K = (u, v) + (head0 / su, head1 / sv)
+
+This module only sequences kernel launches and holds torch-allocated
+buffers; every arithmetic step runs in librdc's HIP kernels.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import inputs, rdc
+
+LAYERS = [("e0a", 32, 32, True), ("e0b", 32, 32, True),
+          ("e1a", 32, 64, True), ("e1b", 64, 64, True),
+          ("e2a", 64, 128, True), ("e2b", 128, 128, True),
+          ("b3a", 128, 128, True), ("b3b", 128, 128, True),
+          ("d2a", 256, 128, True), ("d2b", 128, 128, True),
+          ("d1a", 192, 64, True), ("d1b", 64, 64, True),
+          ("d0a", 96, 32, True), ("d0b", 32, 32, True),
+          ("head", 32, 32, False)]
+IN_C = 32
+HEAD_C = 32
+SU, SV, SP = 1.0, 4.0, 5.0          # input / increment scales of u, v, phi
+THETA = 0.5
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class UNet:
+    """Parameters (fp32 masters, bf16 copies, gradients, Adam moments) in
+    flat device tensors, with per-layer views."""
+
+    def __init__(self, seed: int = 0, device: str = "cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.offsets: Dict[str, Tuple[int, int, int]] = {}   # name -> (w_off, b_off, w_size)
+        off = 0
+        for name, cin, cout, _ in LAYERS:
+            nw = 9 * cout * cin
+            self.offsets[name] = (off, off + nw, nw)
+            off += nw + cout
+        self.nparams = off
+        rng = np.random.default_rng(seed)
+        host = np.zeros(off, dtype=np.float32)
+        for name, cin, cout, _ in LAYERS:
+            wo, bo, nw = self.offsets[name]
+            std = np.sqrt(2.0 / (9 * cin))
+            w = (rng.standard_normal((9, cout, cin)) * std).astype(np.float32)
+            if name == "head":
+                w *= 0.01
+                w[:, 2:, :] = 0.0          # only the (u, v) increments are read
+            host[wo:wo + nw] = w.ravel()
+        self.p = torch.from_numpy(host).to(self.device)
+        self.g = torch.zeros_like(self.p)
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.pb = torch.empty(off, dtype=torch.bfloat16, device=self.device)
+        self.wd = {n: torch.empty(9 * cout * cin, dtype=torch.bfloat16, device=self.device)
+                   for n, cin, cout, _ in LAYERS}
+        self.t = 0
+        self.sync_bf16()
+
+    # -- parameter views
+    def w_ptr(self, name, bf16=True):
+        wo, _, _ = self.offsets[name]
+        base = self.pb if bf16 else self.p
+        return _ptr(base) + wo * base.element_size()
+
+    def b_ptr(self, name):
+        _, bo, _ = self.offsets[name]
+        return _ptr(self.p) + bo * 4
+
+    def gw_ptr(self, name):
+        return _ptr(self.g) + self.offsets[name][0] * 4
+
+    def gb_ptr(self, name):
+        return _ptr(self.g) + self.offsets[name][1] * 4
+
+    def sync_bf16(self):
+        """bf16 copies of the masters (forward) and the flipped, transposed
+        copies (input-gradient convolutions)."""
+        s = self.stream.cuda_stream
+        rdc.nn("to_bf16", _ptr(self.p), _ptr(self.pb), self.nparams, s)
+        for name, cin, cout, _ in LAYERS:
+            rdc.nn("dgrad_weights", self.w_ptr(name, bf16=False), _ptr(self.wd[name]), cout, cin, s)
+
+    def get(self, name) -> Tuple[np.ndarray, np.ndarray]:
+        wo, bo, nw = self.offsets[name]
+        cin, cout = [(ci, co) for n, ci, co, _ in LAYERS if n == name][0]
+        h = self.p.cpu().numpy()
+        return h[wo:wo + nw].reshape(9, cout, cin).copy(), h[bo:bo + cout].copy()
+
+    def set_all(self, params: Dict[str, Tuple[np.ndarray, np.ndarray]]) -> None:
+        h = self.p.cpu().numpy()
+        for name, (W, b) in params.items():
+            wo, bo, nw = self.offsets[name]
+            h[wo:wo + nw] = np.asarray(W, np.float32).ravel()
+            h[bo:bo + len(b)] = np.asarray(b, np.float32)
+        self.p.copy_(self.torch.from_numpy(h))
+        self.sync_bf16()
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, clip=1.0):
+        self.t += 1
+        lr_t = lr * np.sqrt(1 - b2 ** self.t) / (1 - b1 ** self.t)
+        rdc.nn("adam", _ptr(self.p), _ptr(self.g), _ptr(self.m), _ptr(self.v), self.nparams,
+               float(lr_t), b1, b2, eps, clip, self.stream.cuda_stream)
+        self.sync_bf16()
+
+
+class Workspace:
+    """Activation and gradient buffers for N images of H x W (H a multiple of
+    8 and W of 256, so the coarsest level is still a whole number of 32-pixel
+    row segments)."""
+
+    def __init__(self, net: UNet, N: int, H: int, W: int, train: bool = True):
+        torch = net.torch
+        if H % 8 or W % 256 or H < 8:
+            raise ValueError("H must be a multiple of 8 and W of 256")
+        self.net, self.N, self.H, self.W = net, N, H, W
+        bf = lambda h, w, c: torch.zeros((N, h, w, c), dtype=torch.bfloat16, device=net.device)
+        H1, W1, H2, W2, H3, W3 = H // 2, W // 2, H // 4, W // 4, H // 8, W // 8
+        self.shape = {0: (H, W), 1: (H1, W1), 2: (H2, W2), 3: (H3, W3)}
+        a = {}
+        a["x0"] = bf(H, W, IN_C); a["e0a"] = bf(H, W, 32); a["c0"] = bf(H, W, 96)
+        a["d0a"] = bf(H, W, 32); a["d0b"] = bf(H, W, 32); a["head"] = bf(H, W, HEAD_C)
+        a["p1"] = bf(H1, W1, 32); a["e1a"] = bf(H1, W1, 64); a["c1"] = bf(H1, W1, 192)
+        a["d1a"] = bf(H1, W1, 64); a["d1b"] = bf(H1, W1, 64)
+        a["p2"] = bf(H2, W2, 64); a["e2a"] = bf(H2, W2, 128); a["c2"] = bf(H2, W2, 256)
+        a["d2a"] = bf(H2, W2, 128); a["d2b"] = bf(H2, W2, 128)
+        a["p3"] = bf(H3, W3, 128); a["b3a"] = bf(H3, W3, 128); a["b3b"] = bf(H3, W3, 128)
+        self.a = a
+        self.g = {k: torch.zeros_like(v) for k, v in a.items() if k != "x0"} if train else {}
+        if train:
+            need = max(rdc.load().rdc_nn_wgrad_scratch_floats(N, *self._hw(name), cin, cout)
+                       for name, cin, cout, _ in LAYERS)
+            self.scratch = torch.empty(int(need), dtype=torch.float32, device=net.device)
+            self.partial = torch.empty(rdc.load().rdc_nn_loss_blocks(N * H * W),
+                                       dtype=torch.float32, device=net.device)
+
+    def _hw(self, name):
+        lvl = {"e0": 0, "d0": 0, "he": 0, "e1": 1, "d1": 1, "e2": 2, "d2": 2, "b3": 3}[name[:2]]
+        return self.shape[lvl]
+
+    # (tensor name, channel offset, channel count) -> (address, pixel stride)
+    def at(self, buf, name, off=0):
+        t = buf[name]
+        return _ptr(t) + off * 2, t.shape[-1]
+
+
+def _conv(net, ws, name, src, dst, relu=True, store=None):
+    """Forward convolution `name` from (addr, ld) src to (addr, ld) dst."""
+    cin, cout = [(ci, co) for n, ci, co, _ in LAYERS if n == name][0]
+    H, W = ws._hw(name)
+    rdc.nn("conv3x3", src[0], src[1], net.w_ptr(name), net.b_ptr(name), dst[0], dst[1], ws.N,
+           H, W, cin, cout, store or cout, 1 if relu else 0, net.stream.cuda_stream)
+
+
+def forward(net: UNet, ws: Workspace) -> None:
+    """Runs the network on ws.a['x0'] (filled by prep), leaving ws.a['head']."""
+    A, s = ws.a, net.stream.cuda_stream
+    at = lambda n, o=0: ws.at(A, n, o)
+    N = ws.N
+    (H, W), (H1, W1), (H2, W2), (H3, W3) = (ws.shape[i] for i in range(4))
+    _conv(net, ws, "e0a", at("x0"), at("e0a"))
+    _conv(net, ws, "e0b", at("e0a"), at("c0", 64))
+    rdc.nn("pool2", *at("c0", 64), *at("p1"), N, H1, W1, 32, s)
+    _conv(net, ws, "e1a", at("p1"), at("e1a"))
+    _conv(net, ws, "e1b", at("e1a"), at("c1", 128))
+    rdc.nn("pool2", *at("c1", 128), *at("p2"), N, H2, W2, 64, s)
+    _conv(net, ws, "e2a", at("p2"), at("e2a"))
+    _conv(net, ws, "e2b", at("e2a"), at("c2", 128))
+    rdc.nn("pool2", *at("c2", 128), *at("p3"), N, H3, W3, 128, s)
+    _conv(net, ws, "b3a", at("p3"), at("b3a"))
+    _conv(net, ws, "b3b", at("b3a"), at("b3b"))
+    rdc.nn("up2", *at("b3b"), *at("c2"), N, H2, W2, 128, s)
+    _conv(net, ws, "d2a", at("c2"), at("d2a"))
+    _conv(net, ws, "d2b", at("d2a"), at("d2b"))
+    rdc.nn("up2", *at("d2b"), *at("c1"), N, H1, W1, 128, s)
+    _conv(net, ws, "d1a", at("c1"), at("d1a"))
+    _conv(net, ws, "d1b", at("d1a"), at("d1b"))
+    rdc.nn("up2", *at("d1b"), *at("c0"), N, H, W, 64, s)
+    _conv(net, ws, "d0a", at("c0"), at("d0a"))
+    _conv(net, ws, "d0b", at("d0a"), at("d0b"))
+    _conv(net, ws, "head", at("d0b"), at("head"), relu=False)
+
+
+def _layer_bwd(net, ws, name, x, gy, gx=None, relu_y=None):
+    """Gradients of layer `name`: x = its input (addr, ld), gy = output
+    gradient (addr, ld) (already through the ReLU adjoint).  Writes dW, db
+    into net.g and, if gx is given, the input gradient there."""
+    cin, cout = [(ci, co) for n, ci, co, _ in LAYERS if n == name][0]
+    H, W = ws._hw(name)
+    s = net.stream.cuda_stream
+    rdc.nn("conv3x3_wgrad", x[0], x[1], gy[0], gy[1], _ptr(ws.scratch), net.gw_ptr(name), ws.N,
+           H, W, cin, cout, s)
+    rdc.nn("bias_grad", gy[0], gy[1], ws.N * H * W, cout, net.gb_ptr(name), s)
+    if gx is not None:
+        rdc.nn("conv3x3", gy[0], gy[1], _ptr(net.wd[name]), None, gx[0], gx[1], ws.N, H, W,
+               cout, cin, cin, 0, s)
+
+
+def backward(net: UNet, ws: Workspace) -> None:
+    """Back-propagates ws.g['head'] (from the loss) into net.g."""
+    A, G, s = ws.a, ws.g, net.stream.cuda_stream
+    a = lambda n, o=0: ws.at(A, n, o)
+    g = lambda n, o=0: ws.at(G, n, o)
+    N = ws.N
+    (H, W), (H1, W1), (H2, W2), (H3, W3) = (ws.shape[i] for i in range(4))
+    P = lambda lv: N * ws.shape[lv][0] * ws.shape[lv][1]
+
+    def relu_bwd(gname, goff, yname, yoff, c, lvl):
+        rdc.nn("relu_bwd", *g(gname, goff), *a(yname, yoff), P(lvl), c, s)
+
+    _layer_bwd(net, ws, "head", a("d0b"), g("head"), g("d0b"))
+    relu_bwd("d0b", 0, "d0b", 0, 32, 0)
+    _layer_bwd(net, ws, "d0b", a("d0a"), g("d0b"), g("d0a"))
+    relu_bwd("d0a", 0, "d0a", 0, 32, 0)
+    _layer_bwd(net, ws, "d0a", a("c0"), g("d0a"), g("c0"))
+    rdc.nn("up2_bwd", *g("c0"), *g("d1b"), N, H1, W1, 64, s)
+    relu_bwd("d1b", 0, "d1b", 0, 64, 1)
+    _layer_bwd(net, ws, "d1b", a("d1a"), g("d1b"), g("d1a"))
+    relu_bwd("d1a", 0, "d1a", 0, 64, 1)
+    _layer_bwd(net, ws, "d1a", a("c1"), g("d1a"), g("c1"))
+    rdc.nn("up2_bwd", *g("c1"), *g("d2b"), N, H2, W2, 128, s)
+    relu_bwd("d2b", 0, "d2b", 0, 128, 2)
+    _layer_bwd(net, ws, "d2b", a("d2a"), g("d2b"), g("d2a"))
+    relu_bwd("d2a", 0, "d2a", 0, 128, 2)
+    _layer_bwd(net, ws, "d2a", a("c2"), g("d2a"), g("c2"))
+    rdc.nn("up2_bwd", *g("c2"), *g("b3b"), N, H3, W3, 128, s)
+    relu_bwd("b3b", 0, "b3b", 0, 128, 3)
+    _layer_bwd(net, ws, "b3b", a("b3a"), g("b3b"), g("b3a"))
+    relu_bwd("b3a", 0, "b3a", 0, 128, 3)
+    _layer_bwd(net, ws, "b3a", a("p3"), g("b3a"), g("p3"))
+    rdc.nn("pool2_bwd", *g("p3"), *g("c2", 128), N, H3, W3, 128, 1, s)
+    relu_bwd("c2", 128, "c2", 128, 128, 2)
+    _layer_bwd(net, ws, "e2b", a("e2a"), g("c2", 128), g("e2a"))
+    relu_bwd("e2a", 0, "e2a", 0, 128, 2)
+    _layer_bwd(net, ws, "e2a", a("p2"), g("e2a"), g("p2"))
+    rdc.nn("pool2_bwd", *g("p2"), *g("c1", 128), N, H2, W2, 64, 1, s)
+    relu_bwd("c1", 128, "c1", 128, 64, 1)
+    _layer_bwd(net, ws, "e1b", a("e1a"), g("c1", 128), g("e1a"))
+    relu_bwd("e1a", 0, "e1a", 0, 64, 1)
+    _layer_bwd(net, ws, "e1a", a("p1"), g("e1a"), g("p1"))
+    rdc.nn("pool2_bwd", *g("p1"), *g("c0", 64), N, H1, W1, 32, 1, s)
+    relu_bwd("c0", 64, "c0", 64, 32, 0)
+    _layer_bwd(net, ws, "e0b", a("e0a"), g("c0", 64), g("e0a"))
+    relu_bwd("e0a", 0, "e0a", 0, 32, 0)
+    _layer_bwd(net, ws, "e0a", a("x0"), g("e0a"))
+
+
+def prep(net: UNet, ws: Workspace, u_addr, v_addr, phi_addr, pitch, plane_stride):
+    rdc.nn("prep", u_addr, v_addr, phi_addr, pitch, plane_stride, _ptr(ws.a["x0"]), IN_C, ws.N,
+           ws.H, ws.W, SU, SV, SP, net.stream.cuda_stream)
+
+
+def loss_and_grad(net: UNet, ws: Workspace, u, v, ut, vt, pitch, plane_stride,
+                  front_w: float = 4.0) -> float:
+    """Writes d loss / d head into ws.g['head']; returns the loss (syncs)."""
+    rdc.nn("loss", u, v, ut, vt, pitch, plane_stride, _ptr(ws.a["head"]), HEAD_C,
+           _ptr(ws.g["head"]), HEAD_C, ws.N, ws.H, ws.W, SU, SV, THETA, front_w,
+           _ptr(ws.partial), net.stream.cuda_stream)
+    return float(ws.partial.sum().item())
+
+
+def apply(net: UNet, ws: Workspace, u, v, uo, vo, pitch, plane_stride):
+    rdc.nn("apply", u, v, _ptr(ws.a["head"]), HEAD_C, pitch, plane_stride, uo, vo, ws.N, ws.H,
+           ws.W, SU, SV, net.stream.cuda_stream)
+
+
+# ----------------------------------------------------------------- training data and loop
+
+def training_batch_sims(n: int, count: int, seed: int, steps: int) -> List[inputs.Workload]:
+    """Random circuit maps (channels on phi=0.2, diodes and AND junctions)
+    with input disks spread over the first `steps` steps."""
+    return [inputs.circuit(n=n, seed=seed + i, steps=steps, ndisks=max(4, (n // 128) ** 2),
+                           tile=128) for i in range(count)]
+
+
+class Trainer:
+    """Trains the network on pairs (state at t, state at t + K) that the
+    plain stepper generates on the fly from random circuits."""
+
+    def __init__(self, net: UNet, n: int = 256, batch: int = 8, K: int = 50, burn_in: int = 1000,
+                 seed: int = 100):
+        import torch
+        self.net, self.n, self.batch, self.K, self.burn_in = net, n, batch, K, burn_in
+        self.seed = seed
+        self.ws = Workspace(net, batch, n, n, train=True)
+        self.pitch = rdc.pitch_for(n)
+        self.plane = self.pitch * n
+        self.u_in = torch.empty(batch * self.plane, dtype=torch.float32, device=net.device)
+        self.v_in = torch.empty_like(self.u_in)
+        self.round = 0
+        self._new_sims()
+
+    def _new_sims(self):
+        horizon = self.burn_in + 40 * self.K
+        wls = training_batch_sims(self.n, self.batch, self.seed + 1000 * self.round, horizon)
+        self.round += 1
+        self.wls = wls
+        self.sims = rdc.BatchSim([(w.nx, w.ny, w.params) for w in wls])
+        for i, w in enumerate(wls):
+            self.sims.set_phi(i, w.phi)
+        self.now = 0
+        self.sched = sorted((s.step, i, s.cx, s.cy, s.r) for i, w in enumerate(wls)
+                            for s in w.stimuli)
+        self._advance(self.burn_in)
+
+    def _advance(self, n):
+        end = self.now + n
+        while self.now < end:
+            pend = [t for t in self.sched if self.now <= t[0] < end]
+            nxt = pend[0][0] if pend else end
+            if nxt > self.now:
+                self.sims.step(nxt - self.now)
+                self.now = nxt
+            if pend:
+                self.sims.stimulate([(i, cx, cy, r) for (t, i, cx, cy, r) in self.sched
+                                     if t == self.now])
+                self.sched = [x for x in self.sched if x[0] != self.now]
+
+    def pair(self):
+        """Copies the current states to (u_in, v_in), advances K plain steps;
+        returns device addresses (u, v, phi, u_target, v_target)."""
+        if self.now + self.K > self.burn_in + 40 * self.K:
+            self.sims.close()
+            self._new_sims()
+        u, v = self.sims.current()
+        s = self.net.stream.cuda_stream
+        nb = 4 * self.batch * self.plane
+        rdc.rdc_copy(_ptr(self.u_in), _ptr(u), nb, s)
+        rdc.rdc_copy(_ptr(self.v_in), _ptr(v), nb, s)
+        self._advance(self.K)
+        ut, vt = self.sims.current()
+        return (_ptr(self.u_in), _ptr(self.v_in), _ptr(self.sims.planes[4]), _ptr(ut), _ptr(vt))
+
+    def step(self, lr: float = 1e-3) -> float:
+        u, v, phi, ut, vt = self.pair()
+        prep(self.net, self.ws, u, v, phi, self.pitch, self.plane)
+        forward(self.net, self.ws)
+        L = loss_and_grad(self.net, self.ws, u, v, ut, vt, self.pitch, self.plane)
+        backward(self.net, self.ws)
+        self.net.adam(lr=lr)
+        return L
+
+    def close(self):
+        self.sims.close()
+
+
+def train(net: UNet, iters: int, n: int = 256, batch: int = 8, K: int = 50, lr: float = 1e-3,
+          seed: int = 100, log_every: int = 0) -> List[float]:
+    tr = Trainer(net, n=n, batch=batch, K=K, seed=seed)
+    losses = []
+    t0 = time.time()
+    for it in range(iters):
+        lr_it = lr * (0.1 ** (it / max(1, iters)))          # smooth decay to lr/10
+        losses.append(tr.step(lr_it))
+        if log_every and (it + 1) % log_every == 0:
+            print("  iter %d loss %.5f (%.1f s)" % (it + 1, np.mean(losses[-log_every:]),
+                                                      time.time() - t0), flush=True)
+    tr.close()
+    return losses
