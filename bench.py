@@ -89,9 +89,14 @@ def main():
     ap.add_argument("--T", type=int, default=0, help="steps per launch (0 = autotune)")
     ap.add_argument("--rows", type=int, default=0, help="tile rows (0 = autotune)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", default="circuit", choices=("circuit", "batch", "uniform"),
+    ap.add_argument("--workload", default="circuit",
+                    choices=("circuit", "batch", "uniform", "surrogate"),
                     help="circuit: 4096^2 circuit map, 10,000 steps (default); batch: 512-grid "
-                         "sweep, 5,000 steps, batched vs per-grid; uniform: 16384^2, 2,000 steps")
+                         "sweep, 5,000 steps, batched vs per-grid; uniform: 16384^2, 2,000 steps; "
+                         "surrogate: learned coarse stepper trained on 512^2 patches, run on a "
+                         "2048^2 circuit for 50,000 steps against the plain stepper")
+    ap.add_argument("--train-pairs", type=int, default=20000,
+                    help="surrogate: (t, t+50) training pairs of 512^2 patches")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU: this build has no multi-GPU path "
@@ -100,6 +105,8 @@ def main():
         return bench_batch(args)
     if args.workload == "uniform":
         return bench_uniform(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
 
     import torch
     from paper_1901_06535_amd import inputs, rdc
@@ -363,6 +370,140 @@ def bench_uniform(args):
     }
     print(json.dumps(out), flush=True)
     sim.close()
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0    # MI355X dense bf16
+
+
+def bench_surrogate(args):
+    """Learned coarse stepper (K = 50 steps per network step): trained on the
+    GPU on (t, t+50) pairs of 512^2 patches that the plain stepper generates
+    from random circuits (batch 4, Adam), then run on a 2048^2 circuit for
+    50,000 steps with a plain-stepper check every 10 network steps and
+    fallback when the front error exceeds one cell.  Reports its throughput
+    and speedup against the plain stepper on the same grid and schedule, the
+    tracked front error, and the roofline of the heaviest convolution."""
+    import torch
+    from paper_1901_06535_amd import inputs, rdc, surrogate as sg
+
+    if not os.path.exists(rdc.LIB_PATH):
+        from paper_1901_06535_amd import build
+        build.build()
+    K, batch, patch = 50, 4, 512
+    iters = max(1, args.train_pairs // batch)
+    net = sg.UNet(seed=0)
+    tr = sg.Trainer(net, n=patch, batch=batch, K=K, seed=100)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(iters):
+        losses.append(tr.step(1e-3 * (0.1 ** (it / iters))))
+        if (it + 1) % 500 == 0:
+            print("# train iter %d/%d loss %.3g (%.1f s)" % (it + 1, iters,
+                  float(np.mean(losses[-500:])), time.perf_counter() - t0), file=sys.stderr,
+                  flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    tr.close()
+    # held-out pairs: network vs persistence
+    ev = sg.Trainer(net, n=patch, batch=batch, K=K, seed=900000)
+    l_net = l_per = 0.0
+    for _ in range(8):
+        u, v, phi, ut, vt = ev.pair()
+        sg.prep(net, ev.ws, u, v, phi, ev.pitch, ev.plane)
+        sg.forward(net, ev.ws)
+        l_net += sg.loss_and_grad(net, ev.ws, u, v, ut, vt, ev.pitch, ev.plane)
+        ev.ws.a["head"].zero_()
+        l_per += sg.loss_and_grad(net, ev.ws, u, v, ut, vt, ev.pitch, ev.plane)
+    ev.close()
+
+    wl = inputs.circuit(n=2048, seed=1005, steps=50000, ndisks=64, tile=256)
+    zeros = torch.zeros((wl.ny, wl.nx), dtype=torch.float32, device="cuda")
+    # plain stepper on the same schedule
+    sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
+    sim.set_phi(wl.phi)
+    sim.set_block(8)
+    sim.set_tile_rows(56)
+
+    def plain_run():
+        sim.write(zeros, zeros)
+        start = sim.step_index
+        sim.run_schedule([(s.step + start, s.cx, s.cy, s.r) for s in wl.stimuli],
+                         start + wl.steps)
+    plain_run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_run()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_u = sim.current()[0].clone()
+
+    def coarse_run(track):
+        cs = sg.CoarseStepper(net, wl.nx, wl.ny, wl.params, wl.phi, K=K, check_every=10,
+                              track=track)
+        cs.write(zeros, zeros)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cs.advance_to(wl.steps, wl.stimuli)
+        torch.cuda.synchronize()
+        return cs, time.perf_counter() - t
+    cs, _ = coarse_run(False)          # warm-up
+    cs.close()
+    cs, t_coarse = coarse_run(False)
+    stats = dict(cs.stats)
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rdc.nn("front_check", cs.current()[0].data_ptr(), sim.current()[0].data_ptr(), cs.pitch,
+           wl.nx, wl.ny, 0.5, cnt.data_ptr(), cs.net.stream.cuda_stream)
+    final_off = int(cnt.item())
+    # heaviest convolution: events around each launch of a few forwards
+    evs = {}
+    for _ in range(5):
+        sg.forward(net, cs.ws, events=evs)
+    torch.cuda.synchronize()
+    per = {n: float(np.mean([a.elapsed_time(b) for a, b in evs[n][1:]])) / 1e3 for n in evs}
+    heavy = max(per, key=per.get)
+    fl = sg.conv_flops(heavy, cs.ws)
+    fwd_s = sum(per.values())
+    cs.close()
+    cs_tr, _ = coarse_run(True)
+    tracked = dict(cs_tr.stats)
+    cs_tr.close()
+    sim.close()
+    cells = wl.nx * wl.ny
+    value = cells * wl.steps / t_coarse / 1e9
+    achieved = fl / per[heavy] / 1e12
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GCell-updates/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * t_coarse, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 network (fp32 accumulate) + f32 plain checks", "data": "synthetic",
+        "config": {"workload": "surrogate_circuit_2048x2048_50000steps", "K": K,
+                   "check_every": 10, "train_pairs": iters * batch, "train_patch": patch,
+                   "stimuli": len(wl.stimuli), "last_stimulus_step": max(s.step for s in wl.stimuli),
+                   "parallelism": "single GPU"},
+        "speedup_vs_plain": round(t_plain / t_coarse, 4),
+        "plain": {"seconds": round(t_plain, 4), "value": round(cells * wl.steps / t_plain / 1e9, 2),
+                  "unit": "GCell-updates/s", "steps_per_launch": 8, "tile_rows": 56},
+        "coarse_stats": stats,
+        "front_error": {"windows": tracked["tracked_windows"],
+                        "windows_more_than_1_cell_off": tracked["windows_off"],
+                        "max_cells_more_than_1_cell_off": tracked["max_cells_off"],
+                        "final_cells_more_than_1_cell_off": final_off},
+        "training": {"seconds": round(t_train, 2), "iters": iters, "batch": batch,
+                     "pairs_per_s": round(iters * batch / t_train, 1),
+                     "loss_first_100": float(np.mean(losses[:100])),
+                     "loss_last_100": float(np.mean(losses[-100:])),
+                     "held_out_loss_net": l_net / 8, "held_out_loss_persistence": l_per / 8},
+        "forward_ms_2048": round(1e3 * fwd_s, 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 1),
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_conv3x3 (%s)" % heavy, "launch_ms": round(1e3 * per[heavy], 4),
+                     "algorithmic": "2 x 9 x cin x cout FLOP/pixel x %d pixels" % (
+                         cs.ws._hw(heavy)[0] * cs.ws._hw(heavy)[1])},
+        "conv_layers_ms": {n: round(1e3 * t, 4) for n, t in per.items()},
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -286,19 +286,19 @@ rdc_status rdc_nn_conv3x3(const void *x, int32_t ldx, const void *w, const float
  * no ReLU) on the output gradient gives the input gradient. */
 rdc_status rdc_nn_dgrad_weights(const float *w, void *wd, int32_t cout, int32_t cin, void *stream);
 
-/* Floats of scratch rdc_nn_conv3x3_wgrad needs for this shape. */
+/* Floats of scratch rdc_nn_conv3x3_wgrad needs for this shape (the weight
+ * and bias partials of every pixel chunk). */
 int64_t rdc_nn_wgrad_scratch_floats(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout);
 
 /* Weight gradient grad[9][cout][cin] (fp32) = sum over pixels of
- * dy[p][co] * x[p + tap offset][ci]; deterministic (fixed-order reduction of
- * per-chunk partials).  Requires cin, cout % 32 == 0, w % 32 == 0. */
+ * dy[p][co] * x[p + tap offset][ci], and, when gbias is not NULL, the bias
+ * gradient gbias[co] = sum over pixels of dy[p][co].  Deterministic: each
+ * chunk of pixels writes its partials to `scratch`, which are then summed in
+ * a fixed order.  Requires cin, cout % 32 == 0, w % 32 == 0, ldx and lddy
+ * multiples of 8, x and dy 16-byte aligned. */
 rdc_status rdc_nn_conv3x3_wgrad(const void *x, int32_t ldx, const void *dy, int32_t lddy,
-                                float *scratch, float *grad, int32_t n, int32_t h, int32_t w,
-                                int32_t cin, int32_t cout, void *stream);
-
-/* gb[co] = sum over pixels of dy[p][co] (fp32). */
-rdc_status rdc_nn_bias_grad(const void *dy, int32_t lddy, int64_t pixels, int32_t cout, float *gb,
-                            void *stream);
+                                float *scratch, float *grad, float *gbias, int32_t n, int32_t h,
+                                int32_t w, int32_t cin, int32_t cout, void *stream);
 
 /* dst = bf16(src), n elements. */
 rdc_status rdc_nn_to_bf16(const float *src, void *dst, int64_t n, void *stream);
@@ -325,10 +325,18 @@ rdc_status rdc_nn_prep(const float *u, const float *v, const float *phi, int64_t
                        int64_t plane_stride, void *x, int32_t c, int32_t n, int32_t h, int32_t w,
                        float su, float sv, float sp, void *stream);
 
-/* Prediction: uo = u + head[.,0]/su, vo = v + head[.,1]/sv. */
-rdc_status rdc_nn_apply(const float *u, const float *v, const void *head, int32_t ldh,
-                        int64_t pitch, int64_t plane_stride, float *uo, float *vo, int32_t n,
-                        int32_t h, int32_t w, float su, float sv, void *stream);
+/* Prediction, projected onto the states the explicit stepper can continue
+ * from: uo = clamp(u + head[.,0]/su, 0, 1) (the box 0 <= u <= 1 is invariant
+ * under the flow of Eq. (1)) and vo = clamp(v + head[.,1]/sv, 0, (cmax -
+ * phi)/f).  With a = dt (f v + phi) / eps, one forward-Euler step from any
+ * u >= 0 stays above the pole at u = -q of the reaction term iff a < 8 q
+ * (minimum over s = u + q of s - a + 2 a q / s); so cmax = 8 q eps / dt,
+ * less a margin for the diffusion term, is the caller's choice.  phi has the
+ * layout of u.  uo, vo may alias u, v. */
+rdc_status rdc_nn_apply(const float *u, const float *v, const float *phi, const void *head,
+                        int32_t ldh, int64_t pitch, int64_t plane_stride, float *uo, float *vo,
+                        int32_t n, int32_t h, int32_t w, float su, float sv, float f, float cmax,
+                        void *stream);
 
 /* Blocks of per-block loss partials rdc_nn_loss writes for `pixels` pixels. */
 int32_t rdc_nn_loss_blocks(int64_t pixels);
@@ -347,11 +355,21 @@ rdc_status rdc_nn_loss(const float *u, const float *v, const float *ut, const fl
 rdc_status rdc_nn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr_t,
                        float b1, float b2, float eps, float clip, void *stream);
 
-/* Front check between two u planes: adds to *count (device) the number of
- * cells where one side is >= theta and no cell of the other side's 3x3
- * neighbourhood is.  Zero means the fronts agree to within one cell. */
+/* Front check between two u planes (fp32, row pitch `pitch`): adds to
+ * *count (device) the number of cells where one side is >= theta and no
+ * cell of the other side's 3x3 neighbourhood is.  Zero means the fronts agree
+ * to within one cell: the coarse stepper's front-error criterion. */
 rdc_status rdc_nn_front_check(const float *a, const float *b, int64_t pitch, int32_t nx, int32_t ny,
                               float theta, uint32_t *count, void *stream);
+
+/* State check: adds to *count (device) the number of cells the explicit
+ * stepper of Eq. (1) cannot be trusted to continue from: u or v NaN, u
+ * outside [ulo, uhi], or f v + phi > cmax.  With ulo = -q (the reaction
+ * term's pole) and cmax = 8 q eps / dt (see rdc_nn_apply), zero means one
+ * Euler step from every cell stays finite and above the pole. */
+rdc_status rdc_nn_state_check(const float *u, const float *v, const float *phi, int64_t pitch,
+                              int32_t nx, int32_t ny, float ulo, float uhi, float f, float cmax,
+                              uint32_t *count, void *stream);
 
 /* Message of the last failed rdc_nn_* call of this thread. */
 const char *rdc_nn_last_error(void);

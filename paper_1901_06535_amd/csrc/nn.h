@@ -25,22 +25,23 @@ hipError_t conv3x3(const ConvArgs& a, bool relu, bool bias, hipStream_t s);
 
 // Weight gradient of the same convolution: grad[9][cout][cin] (fp32) from
 // x (stride ldx) and dy (stride lddy); `part` is scratch of
-// wgrad_chunks(N, H, W) * 9 * cout * cin floats.  cin, cout % 32 == 0.
+// wgrad_chunks(N, H, W) * 9 * cout * cin floats, `bpart` (optional) of
+// wgrad_chunks(N, H, W) * cout floats for the bias gradient gbias[cout] =
+// sum over pixels of dy.  cin, cout % 32 == 0.
 struct WgradArgs {
     const __bf16* x;
     const __bf16* dy;
     float* part;
+    float* bpart;
     int ldx, lddy;
     int N, H, W;
     int cin, cout;
 };
 int64_t wgrad_chunks(int N, int H, int W);
-hipError_t conv3x3_wgrad(const WgradArgs& a, float* grad, hipStream_t s);
+hipError_t conv3x3_wgrad(const WgradArgs& a, float* grad, float* gbias, hipStream_t s);
 
 hipError_t flip_weights(const float* w, __bf16* wd, int cout, int cin, hipStream_t s);
 hipError_t to_bf16(const float* src, __bf16* dst, int64_t n, hipStream_t s);
-hipError_t bias_grad(const __bf16* dy, int64_t pixels, int ld, int cout, float* gb,
-                     hipStream_t s);
 hipError_t relu_bwd(__bf16* g, int ldg, const __bf16* y, int ldy, int64_t pixels, int c,
                     hipStream_t s);
 hipError_t pool2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo, int c,
@@ -54,9 +55,9 @@ hipError_t up2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int
 hipError_t prep(const float* u, const float* v, const float* phi, int64_t pitch,
                 int64_t plane_stride, __bf16* x, int c, int N, int H, int W, float su, float sv,
                 float sp, hipStream_t s);
-hipError_t apply(const float* u, const float* v, const __bf16* head, int ldh, int64_t pitch,
-                 int64_t plane_stride, float* uo, float* vo, int N, int H, int W, float su,
-                 float sv, hipStream_t s);
+hipError_t apply(const float* u, const float* v, const float* phi, const __bf16* head, int ldh,
+                 int64_t pitch, int64_t plane_stride, float* uo, float* vo, int N, int H, int W,
+                 float su, float sv, float f, float cmax, hipStream_t s);
 int loss_blocks(int64_t pixels);
 hipError_t loss(const float* u, const float* v, const float* ut, const float* vt, int64_t pitch,
                 int64_t plane_stride, const __bf16* head, int ldh, __bf16* g, int ldg, int N,
@@ -66,6 +67,9 @@ hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float l
                 float b2, float eps, float clip, hipStream_t s);
 hipError_t front_check(const float* a, const float* b, int64_t pitch, int nx, int ny,
                        float theta, unsigned int* count, hipStream_t s);
+hipError_t state_check(const float* u, const float* v, const float* phi, int64_t pitch, int nx,
+                       int ny, float ulo, float uhi, float f, float cmax, unsigned int* count,
+                       hipStream_t s);
 
 }  // namespace nn
 }  // namespace rdc

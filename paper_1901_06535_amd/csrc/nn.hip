@@ -134,23 +134,33 @@ __global__ void k_to_bf16(const float* __restrict__ s, __bf16* __restrict__ d, i
 
 // wgrad partials.  Block = one wave; grid.x = chunk of kChunkSegs 32-pixel row
 // segments (a flat index over n, y, x0), grid.y = tap * (cout/32) + co tile,
-// grid.z = ci tile (32).  Writes part[chunk][tap][co][ci] for its tile.
+// grid.z = ci tile (32).  Writes part[chunk][tap][co][ci] for its tile.  The
+// centre-tap blocks of ci tile 0 also sum dY over the chunk's pixels (the bias
+// gradient) into bpart[chunk][co] when bpart is given.
 constexpr int kChunkSegs = 64;
 
 __global__ __launch_bounds__(64) void k_conv3x3_wgrad(WgradArgs a) {
-    __shared__ __bf16 sdy[32][40];   // [co][pixel] (padded rows)
-    __shared__ __bf16 sx[32][40];    // [ci][pixel]
+    // [co][pixel] and [ci][pixel] staging (padded rows); after the chunk
+    // the same memory holds the per-lane bias sums.
+    __shared__ float smem[1280];
+    __bf16 (*sdy)[40] = reinterpret_cast<__bf16 (*)[40]>(smem);
+    __bf16 (*sx)[40] = sdy + 32;
+    float (*sb)[16] = reinterpret_cast<float (*)[16]>(smem);
     const int lane = threadIdx.x;
     const int co_tiles = a.cout >> 5;
     const int tap = blockIdx.y / co_tiles;
     const int co0 = (blockIdx.y % co_tiles) << 5;
     const int ci0 = blockIdx.z << 5;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const bool do_bias = a.bpart != nullptr && tap == 4 && ci0 == 0;
     const int segs_per_row = a.W >> 5;
     const int64_t total_segs = (int64_t)a.N * a.H * segs_per_row;
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    float bsum[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bsum[i] = 0.0f;
     for (int s = 0; s < kChunkSegs; ++s) {
         const int64_t seg = (int64_t)blockIdx.x * kChunkSegs + s;
         if (seg >= total_segs) break;
@@ -175,6 +185,7 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(WgradArgs a) {
             for (int j = 0; j < 8; ++j) {
                 sdy[c + j][p] = gy[j];
                 sx[c + j][p] = gx[j];
+                if (do_bias) bsum[h * 8 + j] += bf2f(gy[j]);
             }
         }
         __syncthreads();
@@ -199,6 +210,19 @@ __global__ __launch_bounds__(64) void k_conv3x3_wgrad(WgradArgs a) {
         const int co = (i >> 2) * 8 + ((lane >> 5) << 2) + (i & 3);
         out[(int64_t)co * a.cin + (lane & 31)] = acc[i];
     }
+    if (do_bias) {
+        // Lane L summed channels 16*h + 8*(L/32) + j over pixel L%32; channel
+        // c is the sum over the 32 lanes of its half, in lane order.
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sb[lane][i] = bsum[i];   // staging is done (barrier above)
+        __syncthreads();
+        if (lane < 32) {
+            const int h = lane >> 4, half = (lane >> 3) & 1, j = lane & 7;
+            float t = 0.0f;
+            for (int l = 0; l < 32; ++l) t += sb[half * 32 + l][h * 8 + j];
+            a.bpart[(int64_t)blockIdx.x * a.cout + co0 + lane] = t;
+        }
+    }
 }
 
 // Sum the wgrad partials over chunks in a fixed order: g[j] = sum_c part[c][j].
@@ -212,22 +236,6 @@ __global__ void k_sum_chunks(const float* __restrict__ part, float* __restrict__
     }
 }
 
-// Bias gradient: gb[co] = sum over pixels of dY[p, co]; one block per channel,
-// fixed-order tree reduction.
-__global__ __launch_bounds__(256) void k_bias_grad(const __bf16* __restrict__ dy, int64_t pixels,
-                                                   int ld, float* __restrict__ gb) {
-    __shared__ float red[256];
-    const int co = blockIdx.x;
-    float s = 0.0f;
-    for (int64_t p = threadIdx.x; p < pixels; p += 256) s += bf2f(dy[p * ld + co]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) gb[co] = red[0];
-}
 
 // ------------------------------------------------------------------ element-wise
 
@@ -345,10 +353,14 @@ __global__ void k_prep(const float* u, const float* v, const float* phi, int64_t
 }
 
 // Prediction: (u, v)_out = (u, v)_in + (du, dv) / (su, sv) from the head's
-// first two channels (fp32 planes, same layout as k_prep).
-__global__ void k_apply(const float* u, const float* v, const __bf16* head, int ldh,
-                        int64_t pitch, int64_t plane_stride, float* uo, float* vo, int N, int H,
-                        int W, float su, float sv) {
+// first two channels (fp32 planes, same layout as k_prep), projected onto the
+// states the explicit stepper can continue from: 0 <= u <= 1 (invariant under
+// the flow of Eq. (1)) and 0 <= v <= (cmax - phi) / f, which keeps one Euler
+// step from any u >= 0 above the pole at u = -q (cmax is set by the caller
+// from eps, q and dt).
+__global__ void k_apply(const float* u, const float* v, const float* phi, const __bf16* head,
+                        int ldh, int64_t pitch, int64_t plane_stride, float* uo, float* vo, int N,
+                        int H, int W, float su, float sv, float f, float cmax) {
     const int64_t total = (int64_t)N * H * W;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
          j += (int64_t)gridDim.x * blockDim.x) {
@@ -357,8 +369,9 @@ __global__ void k_apply(const float* u, const float* v, const __bf16* head, int 
         const int yy = r % H;
         const int n = r / H;
         const int64_t o = n * plane_stride + (int64_t)yy * pitch + xx;
-        uo[o] = u[o] + bf2f(head[j * ldh + 0]) / su;
-        vo[o] = v[o] + bf2f(head[j * ldh + 1]) / sv;
+        const float vcap = fmaxf((cmax - phi[o]) / f, 0.0f);
+        uo[o] = fminf(fmaxf(u[o] + bf2f(head[j * ldh + 0]) / su, 0.0f), 1.0f);
+        vo[o] = fminf(fmaxf(v[o] + bf2f(head[j * ldh + 1]) / sv, 0.0f), vcap);
     }
 }
 
@@ -444,6 +457,24 @@ __global__ __launch_bounds__(256) void k_front_check(const float* a, const float
     if (bad) atomicAdd(count, bad);
 }
 
+// State check: counts cells the explicit stepper cannot continue from:
+// u or v NaN, u outside [ulo, uhi], or f v + phi > cmax.
+__global__ __launch_bounds__(256) void k_state_check(const float* u, const float* v,
+                                                     const float* phi, int64_t pitch, int nx,
+                                                     int ny, float ulo, float uhi, float f,
+                                                     float cmax, unsigned int* count) {
+    const int64_t total = (int64_t)nx * ny;
+    unsigned int bad = 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = (j / nx) * pitch + j % nx;
+        const float uu = u[o];
+        const float c = f * v[o] + phi[o];
+        if (!(uu >= ulo && uu <= uhi && c <= cmax)) ++bad;
+    }
+    if (bad) atomicAdd(count, bad);
+}
+
 inline unsigned grid_for(int64_t n, int block = 256) {
     const int64_t g = (n + block - 1) / block;
     return (unsigned)(g < 16384 ? (g > 0 ? g : 1) : 16384);
@@ -495,7 +526,7 @@ int64_t wgrad_chunks(int N, int H, int W) {
     return (segs + kChunkSegs - 1) / kChunkSegs;
 }
 
-hipError_t conv3x3_wgrad(const WgradArgs& a, float* grad, hipStream_t s) {
+hipError_t conv3x3_wgrad(const WgradArgs& a, float* grad, float* gbias, hipStream_t s) {
     const int64_t chunks = wgrad_chunks(a.N, a.H, a.W);
     const dim3 grid((unsigned)chunks, 9 * (a.cout >> 5), a.cin >> 5);
     hipLaunchKernelGGL(k_conv3x3_wgrad, grid, dim3(64), 0, s, a);
@@ -504,12 +535,10 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, float* grad, hipStream_t s) {
     const int64_t n = 9LL * a.cout * a.cin;
     hipLaunchKernelGGL(k_sum_chunks, dim3(grid_for(n)), dim3(256), 0, s, a.part, grad,
                        (int)chunks, n);
-    return hipGetLastError();
-}
-
-hipError_t bias_grad(const __bf16* dy, int64_t pixels, int ld, int cout, float* gb,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_bias_grad, dim3(cout), dim3(256), 0, s, dy, pixels, ld, gb);
+    e = hipGetLastError();
+    if (e != hipSuccess || !gbias) return e;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(grid_for(a.cout)), dim3(256), 0, s, a.bpart, gbias,
+                       (int)chunks, (int64_t)a.cout);
     return hipGetLastError();
 }
 
@@ -556,11 +585,11 @@ hipError_t prep(const float* u, const float* v, const float* phi, int64_t pitch,
     return hipGetLastError();
 }
 
-hipError_t apply(const float* u, const float* v, const __bf16* head, int ldh, int64_t pitch,
-                 int64_t plane_stride, float* uo, float* vo, int N, int H, int W, float su,
-                 float sv, hipStream_t s) {
-    hipLaunchKernelGGL(k_apply, dim3(grid_for((int64_t)N * H * W)), dim3(256), 0, s, u, v, head,
-                       ldh, pitch, plane_stride, uo, vo, N, H, W, su, sv);
+hipError_t apply(const float* u, const float* v, const float* phi, const __bf16* head, int ldh,
+                 int64_t pitch, int64_t plane_stride, float* uo, float* vo, int N, int H, int W,
+                 float su, float sv, float f, float cmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply, dim3(grid_for((int64_t)N * H * W)), dim3(256), 0, s, u, v, phi,
+                       head, ldh, pitch, plane_stride, uo, vo, N, H, W, su, sv, f, cmax);
     return hipGetLastError();
 }
 
@@ -587,6 +616,14 @@ hipError_t front_check(const float* a, const float* b, int64_t pitch, int nx, in
                        float theta, unsigned int* count, hipStream_t s) {
     hipLaunchKernelGGL(k_front_check, dim3(grid_for((int64_t)nx * ny)), dim3(256), 0, s, a, b,
                        pitch, nx, ny, theta, count);
+    return hipGetLastError();
+}
+
+hipError_t state_check(const float* u, const float* v, const float* phi, int64_t pitch, int nx,
+                       int ny, float ulo, float uhi, float f, float cmax, unsigned int* count,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_state_check, dim3(grid_for((int64_t)nx * ny)), dim3(256), 0, s, u, v,
+                       phi, pitch, nx, ny, ulo, uhi, f, cmax, count);
     return hipGetLastError();
 }
 

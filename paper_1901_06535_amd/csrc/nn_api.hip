@@ -67,12 +67,12 @@ rdc_status rdc_nn_dgrad_weights(const float* w, void* wd, int32_t cout, int32_t 
 
 int64_t rdc_nn_wgrad_scratch_floats(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout) {
     if (n < 1 || h < 1 || w < 32 || cin < 1 || cout < 1) return 0;
-    return rdc::nn::wgrad_chunks(n, h, w) * 9 * (int64_t)cout * cin;
+    return rdc::nn::wgrad_chunks(n, h, w) * (9 * (int64_t)cout * cin + cout);
 }
 
 rdc_status rdc_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_t lddy,
-                                float* scratch, float* grad, int32_t n, int32_t h, int32_t w,
-                                int32_t cin, int32_t cout, void* stream) {
+                                float* scratch, float* grad, float* gbias, int32_t n, int32_t h,
+                                int32_t w, int32_t cin, int32_t cout, void* stream) {
     if (!x || !dy || !scratch || !grad) return nfail("NULL tensor");
     if (n < 1 || h < 1 || w < 32 || w % 32) return nfail("need w a multiple of 32");
     if (cin < 32 || cin % 32 || cout < 32 || cout % 32) return nfail("need cin, cout % 32 == 0");
@@ -82,6 +82,7 @@ rdc_status rdc_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int3
     a.x = static_cast<const __bf16*>(x);
     a.dy = static_cast<const __bf16*>(dy);
     a.part = scratch;
+    a.bpart = gbias ? scratch + rdc::nn::wgrad_chunks(n, h, w) * 9 * (int64_t)cout * cin : nullptr;
     a.ldx = ldx;
     a.lddy = lddy;
     a.N = n;
@@ -89,14 +90,7 @@ rdc_status rdc_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int3
     a.W = w;
     a.cin = cin;
     a.cout = cout;
-    return nhip(rdc::nn::conv3x3_wgrad(a, grad, S(stream)));
-}
-
-rdc_status rdc_nn_bias_grad(const void* dy, int32_t lddy, int64_t pixels, int32_t cout,
-                            float* gb, void* stream) {
-    if (!dy || !gb || pixels < 1 || cout < 1 || lddy < cout) return nfail("bad bias-grad arguments");
-    return nhip(rdc::nn::bias_grad(static_cast<const __bf16*>(dy), pixels, lddy, cout, gb,
-                                   S(stream)));
+    return nhip(rdc::nn::conv3x3_wgrad(a, grad, gbias, S(stream)));
 }
 
 rdc_status rdc_nn_to_bf16(const float* src, void* dst, int64_t n, void* stream) {
@@ -152,14 +146,15 @@ rdc_status rdc_nn_prep(const float* u, const float* v, const float* phi, int64_t
                               su, sv, sp, S(stream)));
 }
 
-rdc_status rdc_nn_apply(const float* u, const float* v, const void* head, int32_t ldh,
-                        int64_t pitch, int64_t plane_stride, float* uo, float* vo, int32_t n,
-                        int32_t h, int32_t w, float su, float sv, void* stream) {
-    if (!u || !v || !head || !uo || !vo || ldh < 2 || n < 1 || h < 1 || w < 1 || pitch < w ||
-        su == 0.0f || sv == 0.0f)
+rdc_status rdc_nn_apply(const float* u, const float* v, const float* phi, const void* head,
+                        int32_t ldh, int64_t pitch, int64_t plane_stride, float* uo, float* vo,
+                        int32_t n, int32_t h, int32_t w, float su, float sv, float f, float cmax,
+                        void* stream) {
+    if (!u || !v || !phi || !head || !uo || !vo || ldh < 2 || n < 1 || h < 1 || w < 1 ||
+        pitch < w || su == 0.0f || sv == 0.0f || !(f > 0.0f))
         return nfail("bad apply arguments");
-    return nhip(rdc::nn::apply(u, v, static_cast<const __bf16*>(head), ldh, pitch, plane_stride,
-                               uo, vo, n, h, w, su, sv, S(stream)));
+    return nhip(rdc::nn::apply(u, v, phi, static_cast<const __bf16*>(head), ldh, pitch,
+                               plane_stride, uo, vo, n, h, w, su, sv, f, cmax, S(stream)));
 }
 
 int32_t rdc_nn_loss_blocks(int64_t pixels) { return pixels < 1 ? 0 : rdc::nn::loss_blocks(pixels); }
@@ -186,6 +181,15 @@ rdc_status rdc_nn_front_check(const float* a, const float* b, int64_t pitch, int
                               int32_t ny, float theta, uint32_t* count, void* stream) {
     if (!a || !b || !count || nx < 1 || ny < 1 || pitch < nx) return nfail("bad front-check arguments");
     return nhip(rdc::nn::front_check(a, b, pitch, nx, ny, theta, count, S(stream)));
+}
+
+rdc_status rdc_nn_state_check(const float* u, const float* v, const float* phi, int64_t pitch,
+                              int32_t nx, int32_t ny, float ulo, float uhi, float f, float cmax,
+                              uint32_t* count, void* stream) {
+    if (!u || !v || !phi || !count || nx < 1 || ny < 1 || pitch < nx || !(ulo <= uhi))
+        return nfail("bad state-check arguments");
+    return nhip(rdc::nn::state_check(u, v, phi, pitch, nx, ny, ulo, uhi, f, cmax, count,
+                                     S(stream)));
 }
 
 }  // extern "C"

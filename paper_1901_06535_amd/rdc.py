@@ -34,10 +34,10 @@ EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_wr
            "rdc_batch_capture", "rdc_graph_launch", "rdc_graph_destroy", "rdc_batch_last_error",
            "rdc_batch_current",
            "rdc_nn_conv3x3", "rdc_nn_dgrad_weights", "rdc_nn_wgrad_scratch_floats",
-           "rdc_nn_conv3x3_wgrad", "rdc_nn_bias_grad", "rdc_nn_to_bf16", "rdc_nn_relu_bwd",
+           "rdc_nn_conv3x3_wgrad", "rdc_nn_to_bf16", "rdc_nn_relu_bwd",
            "rdc_nn_pool2", "rdc_nn_pool2_bwd", "rdc_nn_up2", "rdc_nn_up2_bwd", "rdc_nn_prep",
            "rdc_nn_apply", "rdc_nn_loss_blocks", "rdc_nn_loss", "rdc_nn_adam",
-           "rdc_nn_front_check", "rdc_nn_last_error")
+           "rdc_nn_front_check", "rdc_nn_state_check", "rdc_nn_last_error")
 
 
 class rdc_params(ctypes.Structure):
@@ -111,8 +111,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_nn_conv3x3": (i32, [vp, i32, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32, i32, vp]),
         "rdc_nn_dgrad_weights": (i32, [vp, vp, i32, i32, vp]),
         "rdc_nn_wgrad_scratch_floats": (i64, [i32, i32, i32, i32, i32]),
-        "rdc_nn_conv3x3_wgrad": (i32, [vp, i32, vp, i32, vp, vp, i32, i32, i32, i32, i32, vp]),
-        "rdc_nn_bias_grad": (i32, [vp, i32, i64, i32, vp, vp]),
+        "rdc_nn_conv3x3_wgrad": (i32, [vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, i32, i32, vp]),
         "rdc_nn_to_bf16": (i32, [vp, vp, i64, vp]),
         "rdc_nn_relu_bwd": (i32, [vp, i32, vp, i32, i64, i32, vp]),
         "rdc_nn_pool2": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, vp]),
@@ -121,8 +120,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_nn_up2_bwd": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, vp]),
         "rdc_nn_prep": (i32, [vp, vp, vp, i64, i64, vp, i32, i32, i32, i32, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, vp]),
-        "rdc_nn_apply": (i32, [vp, vp, vp, i32, i64, i64, vp, vp, i32, i32, i32, ctypes.c_float,
-                               ctypes.c_float, vp]),
+        "rdc_nn_apply": (i32, [vp, vp, vp, vp, i32, i64, i64, vp, vp, i32, i32, i32, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),
         "rdc_nn_loss_blocks": (i32, [i64]),
         "rdc_nn_loss": (i32, [vp, vp, vp, vp, i64, i64, vp, i32, vp, i32, i32, i32, i32,
                               ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp,
@@ -130,6 +129,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_nn_adam": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, vp]),
         "rdc_nn_front_check": (i32, [vp, vp, i64, i32, i32, ctypes.c_float, vp, vp]),
+        "rdc_nn_state_check": (i32, [vp, vp, vp, i64, i32, i32, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, vp, vp]),
         "rdc_nn_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

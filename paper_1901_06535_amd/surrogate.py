@@ -170,53 +170,73 @@ class Workspace:
         return _ptr(t) + off * 2, t.shape[-1]
 
 
-def _conv(net, ws, name, src, dst, relu=True, store=None):
-    """Forward convolution `name` from (addr, ld) src to (addr, ld) dst."""
+def conv_flops(name: str, ws: "Workspace") -> int:
+    """Multiply-adds x 2 of forward convolution `name` over the workspace."""
     cin, cout = [(ci, co) for n, ci, co, _ in LAYERS if n == name][0]
     H, W = ws._hw(name)
+    return 2 * 9 * cin * cout * H * W * ws.N
+
+
+def _conv(net, ws, name, src, dst, relu=True, store=None, events=None):
+    """Forward convolution `name` from (addr, ld) src to (addr, ld) dst;
+    with `events` (a dict), HIP events around the launch on the net's stream
+    are appended to events[name]."""
+    cin, cout = [(ci, co) for n, ci, co, _ in LAYERS if n == name][0]
+    H, W = ws._hw(name)
+    if events is not None:
+        e0 = net.torch.cuda.Event(enable_timing=True)
+        e1 = net.torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
     rdc.nn("conv3x3", src[0], src[1], net.w_ptr(name), net.b_ptr(name), dst[0], dst[1], ws.N,
            H, W, cin, cout, store or cout, 1 if relu else 0, net.stream.cuda_stream)
+    if events is not None:
+        e1.record(net.stream)
+        events.setdefault(name, []).append((e0, e1))
 
 
-def forward(net: UNet, ws: Workspace) -> None:
-    """Runs the network on ws.a['x0'] (filled by prep), leaving ws.a['head']."""
+def forward(net: UNet, ws: Workspace, events=None) -> None:
+    """Runs the network on ws.a['x0'] (filled by prep), leaving ws.a['head'].
+    `events`: see _conv."""
     A, s = ws.a, net.stream.cuda_stream
     at = lambda n, o=0: ws.at(A, n, o)
+
+    def conv(name, src, dst, relu=True):
+        _conv(net, ws, name, src, dst, relu=relu, events=events)
+
     N = ws.N
     (H, W), (H1, W1), (H2, W2), (H3, W3) = (ws.shape[i] for i in range(4))
-    _conv(net, ws, "e0a", at("x0"), at("e0a"))
-    _conv(net, ws, "e0b", at("e0a"), at("c0", 64))
+    conv("e0a", at("x0"), at("e0a"))
+    conv("e0b", at("e0a"), at("c0", 64))
     rdc.nn("pool2", *at("c0", 64), *at("p1"), N, H1, W1, 32, s)
-    _conv(net, ws, "e1a", at("p1"), at("e1a"))
-    _conv(net, ws, "e1b", at("e1a"), at("c1", 128))
+    conv("e1a", at("p1"), at("e1a"))
+    conv("e1b", at("e1a"), at("c1", 128))
     rdc.nn("pool2", *at("c1", 128), *at("p2"), N, H2, W2, 64, s)
-    _conv(net, ws, "e2a", at("p2"), at("e2a"))
-    _conv(net, ws, "e2b", at("e2a"), at("c2", 128))
+    conv("e2a", at("p2"), at("e2a"))
+    conv("e2b", at("e2a"), at("c2", 128))
     rdc.nn("pool2", *at("c2", 128), *at("p3"), N, H3, W3, 128, s)
-    _conv(net, ws, "b3a", at("p3"), at("b3a"))
-    _conv(net, ws, "b3b", at("b3a"), at("b3b"))
+    conv("b3a", at("p3"), at("b3a"))
+    conv("b3b", at("b3a"), at("b3b"))
     rdc.nn("up2", *at("b3b"), *at("c2"), N, H2, W2, 128, s)
-    _conv(net, ws, "d2a", at("c2"), at("d2a"))
-    _conv(net, ws, "d2b", at("d2a"), at("d2b"))
+    conv("d2a", at("c2"), at("d2a"))
+    conv("d2b", at("d2a"), at("d2b"))
     rdc.nn("up2", *at("d2b"), *at("c1"), N, H1, W1, 128, s)
-    _conv(net, ws, "d1a", at("c1"), at("d1a"))
-    _conv(net, ws, "d1b", at("d1a"), at("d1b"))
+    conv("d1a", at("c1"), at("d1a"))
+    conv("d1b", at("d1a"), at("d1b"))
     rdc.nn("up2", *at("d1b"), *at("c0"), N, H, W, 64, s)
-    _conv(net, ws, "d0a", at("c0"), at("d0a"))
-    _conv(net, ws, "d0b", at("d0a"), at("d0b"))
-    _conv(net, ws, "head", at("d0b"), at("head"), relu=False)
+    conv("d0a", at("c0"), at("d0a"))
+    conv("d0b", at("d0a"), at("d0b"))
+    conv("head", at("d0b"), at("head"), relu=False)
 
 
-def _layer_bwd(net, ws, name, x, gy, gx=None, relu_y=None):
+def _layer_bwd(net, ws, name, x, gy, gx=None):
     """Gradients of layer `name`: x = its input (addr, ld), gy = output
     gradient (addr, ld) (already through the ReLU adjoint).  Writes dW, db
     into net.g and, if gx is given, the input gradient there."""
     cin, cout = [(ci, co) for n, ci, co, _ in LAYERS if n == name][0]
     H, W = ws._hw(name)
     s = net.stream.cuda_stream
-    rdc.nn("conv3x3_wgrad", x[0], x[1], gy[0], gy[1], _ptr(ws.scratch), net.gw_ptr(name), ws.N,
-           H, W, cin, cout, s)
-    rdc.nn("bias_grad", gy[0], gy[1], ws.N * H * W, cout, net.gb_ptr(name), s)
+    rdc.nn("conv3x3_wgrad", x[0], x[1], gy[0], gy[1], _ptr(ws.scratch), net.gw_ptr(name),
+           net.gb_ptr(name), ws.N, H, W, cin, cout, s)
     if gx is not None:
         rdc.nn("conv3x3", gy[0], gy[1], _ptr(net.wd[name]), None, gx[0], gx[1], ws.N, H, W,
                cout, cin, cin, 0, s)
@@ -285,9 +305,19 @@ def loss_and_grad(net: UNet, ws: Workspace, u, v, ut, vt, pitch, plane_stride,
     return float(ws.partial.sum().item())
 
 
-def apply(net: UNet, ws: Workspace, u, v, uo, vo, pitch, plane_stride):
-    rdc.nn("apply", u, v, _ptr(ws.a["head"]), HEAD_C, pitch, plane_stride, uo, vo, ws.N, ws.H,
-           ws.W, SU, SV, net.stream.cuda_stream)
+def euler_safe_c(params, margin: float = 0.1) -> float:
+    """Largest f v + phi the network's output may carry: one forward-Euler
+    step of Eq. (1) from any u >= 0 stays above the reaction term's pole at
+    u = -q iff dt (f v + phi) / eps < 8 q; `margin` leaves room for the
+    diffusion term."""
+    return (1.0 - margin) * 8.0 * params["q"] * params["eps"] / params["dt"]
+
+
+def apply(net: UNet, ws: Workspace, u, v, phi, uo, vo, pitch, plane_stride, params):
+    """(uo, vo) = (u, v) + the head's increments, projected onto the states
+    the plain stepper can continue from (0 <= u <= 1, f v + phi <= cmax)."""
+    rdc.nn("apply", u, v, phi, _ptr(ws.a["head"]), HEAD_C, pitch, plane_stride, uo, vo, ws.N,
+           ws.H, ws.W, SU, SV, float(params["f"]), euler_safe_c(params), net.stream.cuda_stream)
 
 
 # ----------------------------------------------------------------- training data and loop
@@ -383,3 +413,223 @@ def train(net: UNet, iters: int, n: int = 256, batch: int = 8, K: int = 50, lr: 
                                                       time.time() - t0), flush=True)
     tr.close()
     return losses
+
+
+# ----------------------------------------------------------------- inference with fallback
+
+class CoarseStepper:
+    """Advances one FP32 grid K plain steps at a time with the network, under
+    the plain stepper's supervision (predictor, checked by the plain stepper):
+
+      * a checkpoint always holds a state the plain stepper produced: the
+        start, the plain result of every passed check, the end of every plain
+        window;
+      * every `check_every`-th network step (the first one included) is also
+        computed by the plain stepper from the same input.  The check passes
+        if the two fronts (u >= theta) differ by more than one cell in at most
+        `max_bad` cells and the plain result is one the plain stepper can
+        continue (no NaN, u above the reaction term's pole at -q, f v + phi
+        within the Euler bound 8 q eps / dt less the margin of
+        euler_safe_c -- plain trajectories of the workloads stay below it,
+        while states the network has pushed off them can exceed it and
+        later diverge); the run then continues from the plain result, which
+        becomes the checkpoint;
+      * a failed check discards everything since the checkpoint: the grid is
+        reset to it and the plain stepper replays the steps (and stimuli)
+        since then, and the next `cooldown` windows run plainly before the
+        network is tried again (its next step is checked).  So a network that
+        never passes leaves exactly the plain stepper's trajectory;
+      * stimuli land on their exact step: a window that would cross one is
+        cut short with plain steps.
+
+    `track=True` adds a third grid stepped plainly in lock-step (not part of
+    the method: a measurement of its front error after every window)."""
+
+    def __init__(self, net: UNet, nx: int, ny: int, params, phi, K: int = 50,
+                 check_every: int = 10, theta: float = 0.5, max_bad: int = 0, cooldown: int = 1,
+                 track: bool = False):
+        import torch
+        if nx % 256 or ny % 8:
+            raise ValueError("the coarse stepper needs nx % 256 == 0 and ny % 8 == 0")
+        self.net, self.K, self.check_every = net, K, check_every
+        self.theta, self.max_bad, self.cooldown = theta, max_bad, cooldown
+        self.params = dict(params)
+        self.ulo = -float(params["q"])
+        self.cmax_valid = euler_safe_c(params)
+        self.sim = rdc.Sim(nx, ny, params, "fp32")
+        self.judge = rdc.Sim(nx, ny, params, "fp32")
+        self.ref = rdc.Sim(nx, ny, params, "fp32") if track else None
+        for s in (self.sim, self.judge, self.ref):
+            if s is not None:
+                s.set_phi(phi)
+        self.nx, self.ny, self.pitch = nx, ny, self.sim.pitch
+        self.plane = ny * self.pitch
+        self.ws = Workspace(net, 1, ny, nx, train=False)
+        self.count = torch.zeros(1, dtype=torch.int32, device=net.device)
+        self.ckpt = [torch.empty(self.plane, dtype=torch.float32, device=net.device)
+                     for _ in range(2)]
+        self.ckpt_t = None
+        self.log: List[Tuple[int, list]] = []       # stimuli since the checkpoint
+        self.now = 0
+        # network_steps + plain_steps = steps of the final trajectory;
+        # replayed_steps and discarded_network_steps are work redone or lost
+        # after failed checks.
+        self.stats = dict(network_steps=0, plain_steps=0, replayed_steps=0,
+                          discarded_network_steps=0, checks=0, failed_checks=0, windows=0,
+                          tracked_windows=0, windows_off=0, max_cells_off=0)
+        self._pending = 0          # network steps since the checkpoint
+        self._since_check = None
+        self._cool = 0
+
+    # -- state
+    def write(self, u, v):
+        for s in (self.sim, self.ref):
+            if s is not None:
+                s.write(u, v)
+        self.ckpt_t = None
+
+    def stimulate(self, disks):
+        disks = [tuple(d) for d in disks]
+        for s in (self.sim, self.ref):
+            if s is not None:
+                s.stimulate(disks)
+        if self.ckpt_t is not None:
+            self.log.append((self.now, disks))
+
+    def current(self):
+        return self.sim.current()
+
+    def read(self):
+        return self.sim.read()
+
+    # -- pieces
+    def _copy(self, du, dv, su, sv):
+        s = self.net.stream.cuda_stream
+        nb = 4 * self.plane
+        rdc.rdc_copy(du.data_ptr(), su.data_ptr(), nb, s)
+        rdc.rdc_copy(dv.data_ptr(), sv.data_ptr(), nb, s)
+
+    def _copy_state(self, dst: "rdc.Sim", src: "rdc.Sim"):
+        (du, dv), (su, sv) = dst.current(), src.current()
+        self._copy(du, dv, su, sv)
+
+    def _checkpoint(self):
+        u, v = self.sim.current()
+        self._copy(self.ckpt[0], self.ckpt[1], u, v)
+        self.ckpt_t = self.now
+        self.log = []
+        self._pending = 0
+
+    def _rollback_and_replay(self, until: int):
+        """Reset the grid to the checkpoint and replay plainly to `until`."""
+        u, v = self.sim.current()
+        self._copy(u, v, self.ckpt[0], self.ckpt[1])
+        t = self.ckpt_t
+        for when, disks in self.log:
+            self.sim.step(when - t)
+            t = when
+            self.sim.stimulate(disks)
+        self.sim.step(until - t)
+        st = self.stats
+        st["replayed_steps"] += until - self.ckpt_t
+        st["network_steps"] -= self._pending
+        st["plain_steps"] += self._pending
+        st["discarded_network_steps"] += self._pending
+
+    def _network_step(self):
+        u, v = self.sim.current()
+        prep(self.net, self.ws, u.data_ptr(), v.data_ptr(), self.sim.planes[4].data_ptr(),
+             self.pitch, self.plane)
+        forward(self.net, self.ws)
+        apply(self.net, self.ws, u.data_ptr(), v.data_ptr(), self.sim.planes[4].data_ptr(),
+              u.data_ptr(), v.data_ptr(), self.pitch, self.plane, self.params)
+
+    def _cells_off(self, a: "rdc.Sim", b: "rdc.Sim") -> int:
+        """Cells whose fronts differ by more than one cell between a and b."""
+        self.count.zero_()
+        rdc.nn("front_check", a.current()[0].data_ptr(), b.current()[0].data_ptr(), self.pitch,
+               self.nx, self.ny, self.theta, self.count.data_ptr(), self.net.stream.cuda_stream)
+        return int(self.count.item())
+
+    def _invalid(self, a: "rdc.Sim") -> int:
+        """Cells of a's state the plain stepper cannot be trusted to continue."""
+        self.count.zero_()
+        u, v = a.current()
+        rdc.nn("state_check", u.data_ptr(), v.data_ptr(), a.planes[4].data_ptr(), self.pitch,
+               self.nx, self.ny, self.ulo, 1.5, float(self.params["f"]), self.cmax_valid,
+               self.count.data_ptr(), self.net.stream.cuda_stream)
+        return int(self.count.item())
+
+    def _plain(self, n: int):
+        if n > 0:
+            self.sim.step(n)
+            if self.ref is not None:
+                self.ref.step(n)
+            self.now += n
+            self.stats["plain_steps"] += n
+
+    def _window(self):
+        K, st = self.K, self.stats
+        st["windows"] += 1
+        if self.ckpt_t is None:
+            self._checkpoint()
+        if self._cool > 0:
+            self._cool -= 1
+            self._plain(K)
+            if self._pending == 0:
+                self._checkpoint()
+        else:
+            checked = self._since_check is None or self._since_check >= self.check_every - 1
+            if checked:
+                self._copy_state(self.judge, self.sim)
+                self.judge.step(K)
+                self._network_step()
+                st["checks"] += 1
+                if (self._cells_off(self.judge, self.sim) > self.max_bad
+                        or self._invalid(self.judge) > 0):
+                    st["failed_checks"] += 1
+                    self._rollback_and_replay(self.now + K)
+                    self._cool = self.cooldown
+                    self._since_check = None
+                else:
+                    self._copy_state(self.sim, self.judge)
+                    self._since_check = 0
+                st["plain_steps"] += K
+                self.now += K
+                self._checkpoint()
+            else:
+                self._network_step()
+                st["network_steps"] += K
+                self._pending += K
+                self._since_check += 1
+                self.now += K
+            if self.ref is not None:
+                self.ref.step(K)
+        if self.ref is not None:
+            off = self._cells_off(self.ref, self.sim)
+            st["tracked_windows"] += 1
+            st["windows_off"] += int(off > 0)
+            st["max_cells_off"] = max(st["max_cells_off"], off)
+
+    def advance_to(self, until: int, stimuli=()):
+        """Advance to step index `until`, applying (step, cx, cy, r)
+        stimuli right before the step that leaves their step index."""
+        groups = {}
+        for s in stimuli:
+            t = (s.step, s.cx, s.cy, s.r) if hasattr(s, "step") else tuple(s)
+            groups.setdefault(int(t[0]), []).append(t[1:])
+        for when in sorted(groups) + [until]:
+            if when < self.now or when > until:
+                continue
+            while self.now + self.K <= when:
+                self._window()
+            self._plain(when - self.now)
+            if when in groups:
+                self.stimulate(groups[when])
+            if when == until:
+                break
+
+    def close(self):
+        for s in (self.sim, self.judge, self.ref):
+            if s is not None:
+                s.close()

@@ -115,16 +115,19 @@ def test_wgrad_and_bias_grad(torch, cin, cout, N, H, W, ldx):
     gy, gyr = _bf(torch, rng.standard_normal((N, H, W, cout)))
     need = rdc.load().rdc_nn_wgrad_scratch_floats(N, H, W, cin, cout)
     scratch = torch.empty(int(need), dtype=torch.float32, device="cuda")
-    grads = []
-    for _ in range(2):
+    grads, gbs = [], []
+    for rep in range(3):
         g = torch.full((9 * cout * cin,), 3.0, dtype=torch.float32, device="cuda")
+        gb = torch.full((cout,), 3.0, dtype=torch.float32, device="cuda")
         rdc.nn("conv3x3_wgrad", x.data_ptr(), ldx, gy.data_ptr(), cout, scratch.data_ptr(),
-               g.data_ptr(), N, H, W, cin, cout, _stream(torch))
+               g.data_ptr(), gb.data_ptr() if rep < 2 else None, N, H, W, cin, cout,
+               _stream(torch))
         grads.append(g)
-    gb = torch.zeros(cout, dtype=torch.float32, device="cuda")
-    rdc.nn("bias_grad", gy.data_ptr(), cout, N * H * W, cout, gb.data_ptr(), _stream(torch))
+        gbs.append(gb)
     _sync(torch)
-    assert torch.equal(grads[0], grads[1])                  # deterministic
+    assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])  # deterministic
+    assert torch.equal(gbs[0], gbs[1]) and bool((gbs[2] == 3.0).all())
+    gb = gbs[0]
     w0 = np.zeros((9, cout, cin))
     _, _, ref, rb = unet_ref.conv_grads(xr[..., :cin], w0, np.zeros(cout), gyr)
     _, _, mag, mb = unet_ref.conv_grads(np.abs(xr[..., :cin]), w0, np.zeros(cout), np.abs(gyr))
@@ -197,8 +200,9 @@ def test_prep_apply_loss(torch):
     head, hr = _bf(torch, 0.3 * rng.standard_normal((N, H, W, 32)))
     uo = torch.zeros_like(d["u"])
     vo = torch.zeros_like(d["v"])
-    rdc.nn("apply", d["u"].data_ptr(), d["v"].data_ptr(), head.data_ptr(), 32, pitch, plane,
-           uo.data_ptr(), vo.data_ptr(), N, H, W, su, sv, s)
+    f, cmax = 1.4, 0.3
+    rdc.nn("apply", d["u"].data_ptr(), d["v"].data_ptr(), d["phi"].data_ptr(), head.data_ptr(), 32,
+           pitch, plane, uo.data_ptr(), vo.data_ptr(), N, H, W, su, sv, f, cmax, s)
     g = torch.full((N, H, W, 32), 9.0, dtype=torch.bfloat16, device="cuda")
     nb = rdc.load().rdc_nn_loss_blocks(N * H * W)
     part = torch.zeros(nb, dtype=torch.float32, device="cuda")
@@ -213,8 +217,11 @@ def test_prep_apply_loss(torch):
     assert np.array_equal(xr[..., 1], bfv(np.float32(sv) * v[:, :, :W]))
     assert np.array_equal(xr[..., 2], bfv(np.float32(sp) * phi[:, :, :W]))
     assert (xr[..., 3:] == 0).all()
-    ref_uo = c(u) + hr[..., 0] / su
-    ref_vo = c(v) + hr[..., 1] / sv
+    ref_uo = np.clip(c(u) + hr[..., 0] / su, 0.0, 1.0)
+    vcap = np.maximum((np.float32(cmax) - phi[:, :, :W]) / np.float32(f), 0).astype(np.float64)
+    ref_vo = np.clip(c(v) + hr[..., 1] / sv, 0.0, vcap)
+    assert (ref_uo == 0).any() and (ref_uo == 1).any() and (ref_vo == 0).any()
+    assert (ref_vo == vcap).any()
     got_uo = uo.double().cpu().numpy()[:, :, :W]
     got_vo = vo.double().cpu().numpy()[:, :, :W]
     assert np.abs(got_uo - ref_uo).max() <= 2e-7 * (1 + np.abs(ref_uo).max())
@@ -278,15 +285,37 @@ def test_front_check_counts_cells_more_than_one_cell_off(torch):
     b[:, nx - 1] = 0.9         # a column on the edge
     ref = _front_brute(a[:, :nx], b[:, :nx], 0.5)
     ad, bd = torch.as_tensor(a).cuda(), torch.as_tensor(b).cuda()
-    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
     rdc.nn("front_check", ad.data_ptr(), bd.data_ptr(), pitch, nx, ny, 0.5, cnt.data_ptr(),
            _stream(torch))
-    cnt0 = torch.zeros(1, dtype=torch.int32, device="cuda")
-    rdc.nn("front_check", ad.data_ptr(), ad.data_ptr(), pitch, nx, ny, 0.5, cnt0.data_ptr(),
+    rdc.nn("front_check", ad.data_ptr(), ad.data_ptr(), pitch, nx, ny, 0.5, cnt.data_ptr() + 4,
            _stream(torch))
     _sync(torch)
     assert ref > 0
-    assert int(cnt.item()) == ref and int(cnt0.item()) == 0
+    assert cnt.cpu().numpy().tolist() == [ref, 0]
+
+
+def test_state_check_counts_cells_the_stepper_cannot_continue(torch):
+    ny, nx = 19, 70
+    pitch = rdc.pitch_for(nx)
+    rng = np.random.default_rng(12)
+    u = rng.uniform(0, 1, (ny, pitch)).astype(np.float32)
+    v = rng.uniform(0, 0.2, (ny, pitch)).astype(np.float32)
+    phi = rng.choice([0.054, 0.2], (ny, pitch)).astype(np.float32)
+    u[2, 3], u[4, 5], v[6, 7] = np.nan, -0.0021, np.nan
+    u[8, 9] = 2.5
+    v[10, 11], phi[10, 11] = 0.25, 0.054         # f v + phi = 0.404 > cmax
+    u[:, nx:] = np.nan                            # padding is not part of the grid
+    f, cmax, ulo, uhi = 1.4, 0.352, -0.002, 2.0
+    c = np.float32(f) * v + phi
+    ok = (u >= ulo) & (u <= uhi) & (c <= np.float32(cmax))
+    ref = int((~ok[:, :nx]).sum())
+    d = [torch.as_tensor(t).cuda() for t in (u, v, phi)]
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rdc.nn("state_check", *(t.data_ptr() for t in d), pitch, nx, ny, ulo, uhi, f, cmax,
+           cnt.data_ptr(), _stream(torch))
+    _sync(torch)
+    assert ref >= 5 and int(cnt.item()) == ref
 
 
 # ------------------------------------------------------------------ whole network

@@ -1,0 +1,133 @@
+"""The learned coarse stepper end to end on the GPU: training with the
+library's own forward and backward kernels lowers the loss, the trained
+network beats the no-network baseline (persistence: the state K steps later
+is taken to be the current one), and the plain stepper's checks take over
+when the network is wrong -- then the result is the plain stepper's, bit for
+bit."""
+import numpy as np
+import pytest
+
+from paper_1901_06535_amd import inputs, rdc
+
+pytestmark = pytest.mark.gpu
+
+K = 50
+
+
+@pytest.fixture(scope="module")
+def sg():
+    from paper_1901_06535_amd import surrogate
+    return surrogate
+
+
+@pytest.fixture(scope="module")
+def trained(sg):
+    net = sg.UNet(seed=0)
+    losses = sg.train(net, iters=300, n=256, batch=4, K=K, lr=1e-3, seed=100)
+    return net, losses
+
+
+def _plain_run(wl, until):
+    s = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
+    s.set_phi(wl.phi)
+    s.write(wl.u0, wl.v0)
+    s.run_schedule(wl.stimuli, until)
+    out = s.read()
+    s.close()
+    return out
+
+
+def _workload(seed=7, n=256, steps=1500):
+    return inputs.circuit(n=n, seed=seed, steps=steps, ndisks=4, tile=128)
+
+
+def test_training_lowers_the_loss(trained):
+    _, losses = trained
+    first, last = np.mean(losses[:20]), np.mean(losses[-20:])
+    print("  loss first 20 %.3g, last 20 %.3g" % (first, last))
+    assert np.isfinite(losses).all()
+    assert last < 0.2 * first
+
+
+def test_trained_network_beats_persistence_on_held_out_pairs(sg, trained):
+    """Held-out circuits (other seeds): the network's K-step prediction has a
+    lower loss than persistence, and fewer cells whose front is more than one
+    cell off the plain stepper's."""
+    import torch
+    net, _ = trained
+    ev = sg.Trainer(net, n=256, batch=4, K=K, seed=5000)
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pred_u = torch.empty_like(ev.u_in)
+    pred_v = torch.empty_like(ev.v_in)
+    L_net = L_per = 0.0
+    off_net = off_per = 0
+    for _ in range(6):
+        u, v, phi, ut, vt = ev.pair()
+        sg.prep(net, ev.ws, u, v, phi, ev.pitch, ev.plane)
+        sg.forward(net, ev.ws)
+        L_net += sg.loss_and_grad(net, ev.ws, u, v, ut, vt, ev.pitch, ev.plane)
+        sg.apply(net, ev.ws, u, v, phi, pred_u.data_ptr(), pred_v.data_ptr(), ev.pitch, ev.plane,
+                 inputs.PARAMS_WORKLOAD)
+        for i in range(ev.batch):
+            o = 4 * i * ev.plane
+            for a, tag in ((pred_u.data_ptr() + o, "net"), (u + o, "per")):
+                cnt.zero_()
+                rdc.nn("front_check", a, ut + o, ev.pitch, ev.n, ev.n, sg.THETA, cnt.data_ptr(),
+                       net.stream.cuda_stream)
+                if tag == "net":
+                    off_net += int(cnt.item())
+                else:
+                    off_per += int(cnt.item())
+        ev.ws.a["head"].zero_()
+        L_per += sg.loss_and_grad(net, ev.ws, u, v, ut, vt, ev.pitch, ev.plane)
+    ev.close()
+    print("  held-out loss net %.3g persistence %.3g; cells > 1 cell off: net %d persistence %d"
+          % (L_net, L_per, off_net, off_per))
+    assert L_net < 0.2 * L_per
+    assert off_per > 0 and off_net < off_per
+
+
+@pytest.mark.parametrize("how", ["corrupt_weights", "zero_tolerance"])
+def test_fallback_gives_the_plain_result(sg, how):
+    """A network that is always wrong (head bias of +100 on u) or a front
+    tolerance no result can meet: every check fails, every window ends on the
+    plain stepper's result, and the final state equals a plain run's."""
+    wl = _workload()
+    net = sg.UNet(seed=3)
+    max_bad = 0
+    if how == "corrupt_weights":
+        W, b = net.get("head")
+        b[0] = 100.0
+        net.set_all({"head": (W, b)})
+    else:
+        max_bad = -1
+    cs = sg.CoarseStepper(net, wl.nx, wl.ny, wl.params, wl.phi, K=K, check_every=10,
+                          max_bad=max_bad, cooldown=1)
+    cs.write(wl.u0, wl.v0)
+    cs.advance_to(1237, wl.stimuli)
+    got = cs.read()
+    st = dict(cs.stats)
+    cs.close()
+    ref = _plain_run(wl, 1237)
+    print("  ", st)
+    assert st["network_steps"] == 0 and st["failed_checks"] == st["checks"] > 5
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_trained_network_runs_under_supervision(sg, trained):
+    """With the trained network, the supervised run keeps network steps
+    (checks pass), stays finite, and the tracked front error is reported."""
+    net, _ = trained
+    wl = _workload(seed=11, steps=2000)
+    cs = sg.CoarseStepper(net, wl.nx, wl.ny, wl.params, wl.phi, K=K, check_every=10,
+                          track=True)
+    cs.write(wl.u0, wl.v0)
+    cs.advance_to(2000, wl.stimuli)
+    st = dict(cs.stats)
+    print("  ", st)
+    u, v = cs.read()
+    cs.close()
+    assert np.isfinite(u).all() and np.isfinite(v).all()
+    assert st["network_steps"] + st["plain_steps"] == 2000
+    assert st["network_steps"] > 0
+    assert st["tracked_windows"] == st["windows"]

@@ -337,6 +337,36 @@ def test_inhibitory_background_settles_on_period_two_orbit():
     assert min(seq) < us < max(seq)
 
 
+# ---------------------------------------------------------------- Euler pole bound
+
+def _one_cell_step(u, c, params):
+    """One oracle step of a uniform field (no diffusion) at u with f v + phi = c."""
+    v = (c - 0.054) / params["f"]
+    un, _ = oracle.step(np.full((2, 2), u), np.full((2, 2), v), np.full((2, 2), 0.054), params)
+    return un[0, 0]
+
+
+def test_euler_step_from_nonnegative_u_stays_above_the_pole_iff_a_below_8q():
+    """With a = dt (f v + phi) / eps, the reaction term's part of one Euler
+    step maps u to u - a (u - q)/(u + q); over u >= 0 its minimum, at
+    u + q = sqrt(2 a q), is 2 sqrt(2 a q) - a - q, above the pole -q iff
+    a < 8 q.  The oracle's step (which adds dt (u - u^2) / eps >= 0) agrees:
+    below the bound no u >= 0 steps past -q, and 10% above it the minimising
+    u does.  The coarse stepper caps f v + phi of its outputs from this."""
+    from paper_1901_06535_amd import surrogate
+    q, eps, dt = P["q"], P["eps"], P["dt"]
+    c8 = 8 * q * eps / dt
+    assert surrogate.euler_safe_c(P, margin=0.0) == pytest.approx(c8, rel=1e-15)
+    for frac in (0.5, 0.9, 0.99):
+        c = frac * c8
+        us = np.concatenate([np.linspace(0, 0.05, 2001), np.geomspace(1e-9, 1.0, 400)])
+        lo = min(_one_cell_step(x, c, P) for x in us)
+        assert lo > -q, (frac, lo)
+    a = dt * 1.1 * c8 / eps
+    ustar = np.sqrt(2 * a * q) - q
+    assert _one_cell_step(ustar, 1.1 * c8, P) < -q
+
+
 # ---------------------------------------------------------------- stimulation
 
 def test_disk_cell_counts_match_gauss_circle():
