@@ -17,7 +17,6 @@ FP64 CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,14 +34,6 @@ FLOP_PER_UPDATE = 21            # canonical per-cell expression, divide counted 
 BYTES_PER_CELL_LAUNCH = 20      # read u, v, phi (12 B) + write u', v' (8 B), FP32
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1901_06535_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1901_06535_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(key: str):
     """Per-launch HBM bytes from rocprofv3 counters, if they were taken on the
     current kernel source (else None)."""
@@ -52,7 +43,8 @@ def load_traffic(key: str):
     with open(path) as fh:
         rec = json.load(fh)
     ent = rec.get(key)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    from paper_1901_06535_amd.profile_kernels import source_hash
+    if not ent or ent.get("source_hash") != source_hash():
         return None
     return ent
 

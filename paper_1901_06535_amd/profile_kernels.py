@@ -9,15 +9,101 @@ reference reading that scales memory counters to bytes).  Under
     rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_1901_06535_amd.profile_kernels
 
 each dispatch gets its own counter values.  Prints what it launched.
+
+    python3 -m paper_1901_06535_amd.profile_kernels --summarize FETCH.csv WRITE.csv
+
+turns the two counter runs' CSV files into per-launch HBM bytes: each
+kernel's average FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what
+the same counters read for the 1 GiB copy, written to profiles/traffic.json
+with the hash of the stepper's kernel sources (readers ignore entries taken
+on other sources) and printed as a table;
+
+    python3 -m paper_1901_06535_amd.profile_kernels --stats KERNEL_STATS.csv
+
+prints the top rows of a rocprofv3 --stats kernel table.
 """
 from __future__ import annotations
 
 import argparse
+import collections
+import csv
+import hashlib
 import json
+import os
+import re
 
 import numpy as np
 
 from . import inputs, rdc
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+STEPPER_SOURCES = ("cell.h", "tile.h", "kernels.h", "kernels.hip")
+
+
+def source_hash() -> str:
+    """Hash of the sources the stepper kernels are compiled from."""
+    h = hashlib.sha256()
+    for f in STEPPER_SOURCES:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _short(name: str) -> str:
+    n = name.replace("void ", "").replace("rdc::nn::(anonymous namespace)::", "")
+    n = n.replace("rdc::(anonymous namespace)::", "")
+    m = re.match(r"k_stepT<(\d+), (\d+), (\w+)>", n)
+    if m:
+        return "k_stepT<T=%s,rows=%d%s>" % (m.group(1), 8 * int(m.group(2)),
+                                           ",arrival" if m.group(3) == "true" else "")
+    m = re.match(r"k_step1<(\w+), (\w+)>", n)
+    if m:
+        return "k_step1<%s%s>" % (m.group(1), ",arrival" if m.group(2) == "true" else "")
+    return re.sub(r"\(.*", "", n)
+
+
+def _counter_means(path: str, counter: str):
+    vals = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            vals[_short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
+
+
+def stats(path: str, top: int = 20) -> None:
+    """Print the top rows of a rocprofv3 --stats kernel table."""
+    rows = [(_short(r["Name"]), int(r["Calls"]), float(r["AverageNs"]), float(r["Percentage"]))
+            for r in csv.DictReader(open(path))]
+    for name, calls, avg, pct in rows[:top]:
+        print("%-40s calls=%6d avg_us=%9.2f pct=%6.2f" % (name[:40], calls, avg / 1e3, pct))
+
+
+def summarize(fetch_csv: str, write_csv: str, out_json: str) -> None:
+    f = _counter_means(fetch_csv, "FETCH_SIZE")
+    w = _counter_means(write_csv, "WRITE_SIZE")
+    gib_kib = (1 << 30) / 1024
+    sf, sw = gib_kib / f["k_copy16"][0], gib_kib / w["k_copy16"][0]
+    rec = {"_note": "Per-launch HBM bytes of each kernel from rocprofv3 FETCH_SIZE and "
+                    "WRITE_SIZE (KiB per dispatch), scaled by the readings of a 1 GiB copy "
+                    "kernel; source_hash identifies the stepper sources the counters were "
+                    "taken on.",
+           "scale": {"fetch": round(sf, 4), "write": round(sw, 4)}}
+    print("scale FETCH x%.4f WRITE x%.4f (copy kernel, 1 GiB read + 1 GiB written)" % (sf, sw))
+    h = source_hash()
+    for k in sorted(f):
+        if k not in w or k == "k_copy16" or not k.startswith("k_step"):
+            continue
+        rd, wr = f[k][0] * 1024 * sf, w[k][0] * 1024 * sw
+        m = re.match(r"k_stepT<T=(\d+),rows=(\d+)>$", k)
+        key = ("stepT_T%s_r%s_4096x4096" % m.groups()) if m else (
+            "step1_16384x16384" if k == "k_step1<float>" else None)
+        print("%-28s n=%2d fetch_KiB=%12.1f write_KiB=%12.1f -> read_MB=%9.1f written_MB=%9.1f"
+              % (k, f[k][1], f[k][0], w[k][0], rd / 1e6, wr / 1e6))
+        if key:
+            rec[key] = {"kernel": k, "bytes_read": int(rd), "bytes_written": int(wr),
+                        "bytes_per_launch": int(rd + wr), "source_hash": h}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
 
 CANDIDATES = [(T, r) for T in (4, 6, 8) for r in (48, 56, 64, 80)]
 LAUNCHES = 4
@@ -28,7 +114,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--big", type=int, default=16384)
+    ap.add_argument("--summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--stats", metavar="KERNEL_STATS_CSV")
+    ap.add_argument("--top", type=int, default=20)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "profiles",
+                                                  "traffic.json"))
     args = ap.parse_args()
+    if args.summarize:
+        return summarize(args.summarize[0], args.summarize[1], args.out)
+    if args.stats:
+        return stats(args.stats, args.top)
     log = []
     wl = inputs.circuit(n=args.n, seed=1002, steps=10000, ndisks=256)
     sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
