@@ -123,7 +123,7 @@ def main():
         sched = [(s.step + start, s.cx, s.cy, s.r) for s in wl.stimuli]
         sim.run_schedule(sched, start + wl.steps)
 
-    # -- pick steps per launch and tile height by timing the real grid
+    # -- pick steps per launch and tile height by timing this grid's shape
     def time_steps(T, rows, n):
         sim.set_block(T)
         sim.set_tile_rows(rows)
@@ -136,15 +136,14 @@ def main():
         e1.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
-    cands = [(args.T, args.rows)] if args.T and args.rows else [
-        (T, r) for T in ((args.T,) if args.T else (4, 6, 8))
-        for r in ((args.rows,) if args.rows else (48, 56, 64, 80))]
-    tune = {}
-    for T, r in cands:
-        n_t = 48 * T
-        tune["T%d_r%d" % (T, r)] = time_steps(T, r, n_t) / n_t    # seconds per Euler step
-    best = min(tune, key=tune.get)
-    T, rows = (int(x) for x in best[1:].split("_r"))
+    if args.T and args.rows:
+        T, rows = args.T, args.rows
+        tune = {}
+    else:
+        rec = sim.autotune(Ts=(args.T,) if args.T else (4, 6, 8),
+                           rows=(args.rows,) if args.rows else (48, 56, 64, 80),
+                           launches=48, use_cache=False)
+        T, rows, tune = rec["T"], rec["rows"], rec["table"]
     sim.set_block(T)
     sim.set_tile_rows(rows)
 
@@ -195,7 +194,7 @@ def main():
                          algorithmic="%d FLOP/update x %d updates; %d B/cell x %d cells"
                                      % (FLOP_PER_UPDATE, cells * T, BYTES_PER_CELL_LAUNCH, cells)),
         "roofline_other": other,
-        "tuning_us_per_step": {k: round(1e6 * v, 2) for k, v in tune.items()},
+        "tuning_us_per_step": tune,
         "wall_s": round(wall, 3),
     }
     if not args.no_cpu:
@@ -236,22 +235,9 @@ def bench_batch(args):
             rdc.rdc_copy(plane.data_ptr(), zeros.data_ptr(), nbytes, stream)
         b.stimulate(disks)
 
-    # autotune the batched launch on the real sweep
-    tune = {}
-    for T in (4, 6, 8):
-        for rows in (48, 56, 64):
-            b.set_block(T, rows)
-            reset()
-            b.step(2 * T)
-            e0, e1 = _events()
-            e0.record(b.stream)
-            b.step(24 * T)
-            e1.record(b.stream)
-            e1.synchronize()
-            tune["T%d_r%d" % (T, rows)] = e0.elapsed_time(e1) / 1e3 / (24 * T)
-    best = min(tune, key=tune.get)
-    T, rows = (int(x) for x in best[1:].split("_r"))
-    b.set_block(T, rows)
+    # autotune the batched launch on the sweep's shapes
+    rec = b.autotune(launches=24, use_cache=False)
+    T, rows, tune = rec["T"], rec["rows"], rec["table"]
     g = b.capture(steps)
     for _ in range(args.warmup):
         reset()
@@ -314,7 +300,7 @@ def bench_batch(args):
         "speedup_vs_per_grid": round(value / single, 2),
         "diverged_grids": len(diverged),
         "diverged_eps_max": round(max(sims[i].params["eps"] for i in diverged), 5) if diverged else None,
-        "tuning_us_per_step": {k: round(1e6 * v, 2) for k, v in tune.items()},
+        "tuning_us_per_step": tune,
     }
     print(json.dumps(out), flush=True)
 

@@ -141,8 +141,9 @@ rdc_status rdc_read(rdc_ctx *ctx, void *u, void *v, int64_t pitch, rdc_where whe
  * expression and bit-identical results.  Errors: RDC_E_INVAL outside 0..8. */
 rdc_status rdc_set_block(rdc_ctx *ctx, int32_t T);
 
-/* Rows of a temporal-blocking tile: 0 (auto) or one of the supported tile
- * heights reported by rdc_tile_rows_supported.  Errors: RDC_E_INVAL. */
+/* Rows of a temporal-blocking tile: 0 (auto: 56 rows) or one of the
+ * supported tile heights reported by rdc_tile_rows_supported (the Python
+ * autotuner times them on the grid's shape).  Errors: RDC_E_INVAL. */
 rdc_status rdc_set_tile_rows(rdc_ctx *ctx, int32_t rows);
 
 /* Non-zero if `rows` is a tile height rdc_set_tile_rows accepts. */
@@ -160,6 +161,17 @@ rdc_status rdc_current(rdc_ctx *ctx, void **u_dev, void **v_dev);
  * multiple of 64 and >= nx.  FP32 and FP64 contexts both support it.
  * Errors: RDC_E_INVAL for a bad pitch or alignment. */
 rdc_status rdc_set_arrival(rdc_ctx *ctx, int32_t *arrival_dev, int64_t pitch, double theta);
+
+/* Timelapse (Sec. 3.1: u recorded over time at a user-set rate, shown over
+ * the static substrate).  Attach (or, with NULL, detach) a caller-owned
+ * device plane of the context's precision that holds the maximum of u over
+ * the recorded frames: attaching copies the current u into it (the first
+ * frame), and after every step that leaves a step index that is a multiple
+ * of `rate`, each cell takes max(plane, u).  Fused into the stepping
+ * kernels' epilogue (like the arrival map), so no frame is copied out.
+ * `pitch` must be a multiple of 64 and >= nx; the plane 256-byte aligned.
+ * Errors: RDC_E_INVAL for rate < 1, a bad pitch or alignment. */
+rdc_status rdc_set_timelapse(rdc_ctx *ctx, void *timelapse_dev, int64_t pitch, int32_t rate);
 
 /* Number of steps taken since rdc_create.  Errors: RDC_E_INVAL for NULL. */
 rdc_status rdc_get_step(const rdc_ctx *ctx, int64_t *step);

@@ -143,6 +143,16 @@ class Run:
         self.unstable = np.zeros(self.u.shape, dtype=np.uint8) if track_unstable else None
         self.unstable_from = int(unstable_from)
         self._first = ctypes.c_int64(-1)
+        self.timelapse = None
+        self.timelapse_rate = 0
+
+    def track_timelapse(self, rate: int) -> None:
+        """Timelapse (Sec. 3.1): the maximum of u over frames recorded every
+        `rate` steps, starting with the current state as the first frame; a
+        frame is taken after every step that leaves a step index divisible by
+        `rate`."""
+        self.timelapse = self.u.copy()
+        self.timelapse_rate = int(rate)
 
     @property
     def first_unstable(self) -> int:
@@ -154,6 +164,17 @@ class Run:
     def advance(self, n: int) -> None:
         if n <= 0:
             return
+        if self.timelapse is not None:
+            end = self.step_index + int(n)
+            while self.step_index < end:
+                nxt = min(end, (self.step_index // self.timelapse_rate + 1) * self.timelapse_rate)
+                self._advance(nxt - self.step_index)
+                if self.step_index % self.timelapse_rate == 0:
+                    np.maximum(self.timelapse, self.u, out=self.timelapse)
+            return
+        self._advance(n)
+
+    def _advance(self, n: int) -> None:
         lib = _load()
         p = _params(self.params)
         ap = _ptr(self.arrival, ctypes.c_int32) if self.arrival is not None else None

@@ -28,6 +28,9 @@ struct rdc_ctx {
     int32_t* arrival = nullptr;
     int64_t apitch = 0;
     double theta = 0.5;
+    void* tl = nullptr;             // timelapse plane (running max of u over frames)
+    int64_t tpitch = 0;
+    int32_t tl_rate = 1;
     std::string err;
 };
 
@@ -102,9 +105,12 @@ rdc::StepArgs<Real> step_args(const rdc_ctx* c) {
     a.u_out = static_cast<Real*>(c->u[c->cur ^ 1]);
     a.v_out = static_cast<Real*>(c->v[c->cur ^ 1]);
     a.arrival = c->arrival;
+    a.tl = static_cast<Real*>(c->tl);
     a.flag = c->d_flag;
     a.pitch = c->pitch;
     a.apitch = c->apitch;
+    a.tpitch = c->tpitch;
+    a.tl_rate = c->tl_rate;
     a.nx = c->nx;
     a.ny = c->ny;
     a.step0 = static_cast<int>(c->step);
@@ -383,6 +389,33 @@ rdc_status rdc_set_arrival(rdc_ctx* c, int32_t* arrival, int64_t pitch, double t
         e = rdc::launch_arrival_init(static_cast<const float*>(c->u[c->cur]), c->pitch, c->nx,
                                      c->ny, (float)theta, arrival, pitch, (int)c->step, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "arrival init launch");
+    return RDC_OK;
+}
+
+rdc_status rdc_set_timelapse(rdc_ctx* c, void* tl, int64_t pitch, int32_t rate) {
+    if (!c) return RDC_E_INVAL;
+    if (!tl) {
+        c->tl = nullptr;
+        c->tpitch = 0;
+        c->tl_rate = 1;
+        return RDC_OK;
+    }
+    if (rate < 1) return fail(c, RDC_E_INVAL, "timelapse rate must be >= 1");
+    if (pitch < c->nx || pitch % 64 != 0)
+        return fail(c, RDC_E_INVAL, "timelapse pitch must be >= nx and a multiple of 64");
+    if (!aligned256(tl)) return fail(c, RDC_E_INVAL, "timelapse plane must be 256-byte aligned");
+    DeviceGuard g(c->device);
+    hipError_t e;
+    if (c->dtype == RDC_FP64)
+        e = rdc::launch_copy_plane(static_cast<const double*>(c->u[c->cur]), c->pitch, c->nx,
+                                   c->ny, static_cast<double*>(tl), pitch, c->stream);
+    else
+        e = rdc::launch_copy_plane(static_cast<const float*>(c->u[c->cur]), c->pitch, c->nx,
+                                   c->ny, static_cast<float*>(tl), pitch, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "timelapse init launch");
+    c->tl = tl;
+    c->tpitch = pitch;
+    c->tl_rate = rate;
     return RDC_OK;
 }
 

@@ -66,9 +66,12 @@ void k_batch_stepT(BatchArgs b) {
     a.u_out = b.u_out + sd.offset;
     a.v_out = b.v_out + sd.offset;
     a.arrival = nullptr;
+    a.tl = nullptr;
     a.flag = b.flags + it.sim;
     a.pitch = sd.pitch;
     a.apitch = 0;
+    a.tpitch = 0;
+    a.tl_rate = 1;
     a.nx = sd.nx;
     a.ny = sd.ny;
     a.step0 = 0;

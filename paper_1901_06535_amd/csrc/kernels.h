@@ -19,11 +19,14 @@ struct StepArgs {
     Real* u_out;        // next u plane
     Real* v_out;        // next v plane
     int32_t* arrival;   // optional first-arrival plane (nullptr = off)
+    Real* tl;           // optional timelapse plane: running max of u over frames (nullptr = off)
     int* flag;          // sticky non-finite flag (device int)
     int64_t pitch;      // elements per row of u, v, phi
     int64_t apitch;     // elements per row of arrival
+    int64_t tpitch;     // elements per row of tl
     int nx, ny;
-    int step0;          // state index before this launch (for arrival times)
+    int step0;          // state index before this launch (for arrival times and frames)
+    int tl_rate;        // a frame is taken after every step whose index is a multiple
     Real theta;         // arrival threshold
     Consts<Real> k;
 };
@@ -54,6 +57,12 @@ hipError_t launch_arrival_init(const float* u, int64_t pitch, int nx, int ny, fl
                                int32_t* arrival, int64_t apitch, int step, hipStream_t s);
 hipError_t launch_arrival_init(const double* u, int64_t pitch, int nx, int ny, double theta,
                                int32_t* arrival, int64_t apitch, int step, hipStream_t s);
+
+// tl := u over the grid (the timelapse's first frame).
+hipError_t launch_copy_plane(const float* u, int64_t pitch, int nx, int ny, float* tl,
+                             int64_t tpitch, hipStream_t s);
+hipError_t launch_copy_plane(const double* u, int64_t pitch, int nx, int ny, double* tl,
+                             int64_t tpitch, hipStream_t s);
 
 // *flag := 0 (a kernel, not a memset, so the call is safe under graph capture).
 hipError_t launch_clear_flag(int* flag, hipStream_t s);

@@ -39,7 +39,7 @@ constexpr int kStep1Rows = RDC_STEP1_ROWS;   // rows one block marches down
 // row resources and store nothing.
 // One output row: north / centre / south rows of u (this lane's 4 cells),
 // v and phi of the centre row; east / west across lanes, edge lanes load.
-template <typename Real, bool ARR>
+template <typename Real, bool OUT>
 __device__ __forceinline__ void step1_row(const StepArgs<Real>& a, int y, int x0, int lane,
                                           int rb, const V4<Real>& un, const V4<Real>& uc,
                                           const V4<Real>& us, const V4<Real>& vc,
@@ -78,11 +78,17 @@ __device__ __forceinline__ void step1_row(const StepArgs<Real>& a, int y, int x0
             }
         }
     }
-    if (ARR) {
+    if (OUT && a.arrival) {
         int32_t* ar = a.arrival + (int64_t)y * a.apitch + x0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
             if (x0 + c < nx && ar[c] == kNever && uo.e[c] >= a.theta) ar[c] = a.step0 + 1;
+    }
+    if (OUT && a.tl && (a.step0 + 1) % a.tl_rate == 0) {
+        Real* tp = a.tl + (int64_t)y * a.tpitch + x0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (x0 + c < nx && uo.e[c] > tp[c]) tp[c] = uo.e[c];
     }
 }
 
@@ -93,7 +99,7 @@ __device__ __forceinline__ void step1_row(const StepArgs<Real>& a, int y, int x0
 // wave's edge lanes read one extra cell.  Lanes past the east edge still run
 // (the lane exchange needs the whole wave) but load through bounds-checked
 // row resources and store nothing.
-template <typename Real, bool ARR>
+template <typename Real, bool OUT>
 __global__ __launch_bounds__(kStep1Threads) void k_step1(StepArgs<Real> a) {
     const int x0 = (blockIdx.x * kStep1Threads + threadIdx.x) * 4;
     const int lane = threadIdx.x & 63;
@@ -116,8 +122,8 @@ __global__ __launch_bounds__(kStep1Threads) void k_step1(StepArgs<Real> a) {
         const V4<Real> us2 = load(a.u, y1 + 1 < ny ? y1 + 1 : y1);
         const V4<Real> vc = load(a.v, y), pc = load(a.phi, y);
         const V4<Real> vc1 = load(a.v, y1), pc1 = load(a.phi, y1);
-        step1_row<Real, ARR>(a, y, x0, lane, rb, un, uc, us, vc, pc, bad);
-        if (two) step1_row<Real, ARR>(a, y1, x0, lane, rb, uc, us, us2, vc1, pc1, bad);
+        step1_row<Real, OUT>(a, y, x0, lane, rb, un, uc, us, vc, pc, bad);
+        if (two) step1_row<Real, OUT>(a, y1, x0, lane, rb, uc, us, us2, vc1, pc1, bad);
         un = us;
         uc = us2;
     }
@@ -126,8 +132,8 @@ __global__ __launch_bounds__(kStep1Threads) void k_step1(StepArgs<Real> a) {
 
 // ---------------------------------------------------------------- T steps
 
-template <int T, int R, bool ARR>
-__global__ __launch_bounds__(kTileWaves * 64, (tile_waves_per_simd<R, ARR>()))
+template <int T, int R, bool OUT>
+__global__ __launch_bounds__(kTileWaves * 64, (tile_waves_per_simd<R, OUT>()))
 void k_stepT(StepArgs<float> a, int tiles_x, int ntiles, int per_xcd) {
     __shared__ float4 lds[kTileWaves * R][64];
     // Workgroups are dealt to the 8 XCDs round-robin; renumber so that each
@@ -137,7 +143,7 @@ void k_stepT(StepArgs<float> a, int tiles_x, int ntiles, int per_xcd) {
     const int b = blockIdx.x;
     const int tile = (b & 7) * per_xcd + (b >> 3);
     if (tile >= ntiles) return;
-    step_tile<T, R, ARR>(a, tile % tiles_x, tile / tiles_x, lds);
+    step_tile<T, R, OUT>(a, tile % tiles_x, tile / tiles_x, lds);
 }
 
 // ---------------------------------------------------------------- stimulation etc.
@@ -203,11 +209,23 @@ __global__ __launch_bounds__(256) void k_copy16(const float4* __restrict__ src,
     }
 }
 
+// tl := u, row by row (pitches may differ).
+template <typename Real>
+__global__ __launch_bounds__(256) void k_copy_plane(const Real* u, int64_t pitch, int nx, int ny,
+                                                    Real* tl, int64_t tpitch) {
+    const int64_t n = (int64_t)nx * ny;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = j / nx, x = j % nx;
+        tl[y * tpitch + x] = u[y * pitch + x];
+    }
+}
+
 template <typename Real>
 hipError_t step1_impl(const StepArgs<Real>& a, hipStream_t s) {
     const dim3 grid((a.nx + kStep1Threads * 4 - 1) / (kStep1Threads * 4),
                     (a.ny + kStep1Rows - 1) / kStep1Rows);
-    if (a.arrival)
+    if (a.arrival || a.tl)
         hipLaunchKernelGGL((k_step1<Real, true>), grid, dim3(kStep1Threads), 0, s, a);
     else
         hipLaunchKernelGGL((k_step1<Real, false>), grid, dim3(kStep1Threads), 0, s, a);
@@ -224,7 +242,7 @@ hipError_t stepT_impl(const StepArgs<float>& a, hipStream_t s) {
     const int ntiles = tiles_x * tiles_y;
     const int per_xcd = (ntiles + 7) / 8;
     const dim3 grid(8 * per_xcd), block(kTileWaves * 64);
-    if (a.arrival)
+    if (a.arrival || a.tl)
         hipLaunchKernelGGL((k_stepT<T, R, true>), grid, block, 0, s, a, tiles_x, ntiles, per_xcd);
     else
         hipLaunchKernelGGL((k_stepT<T, R, false>), grid, block, 0, s, a, tiles_x, ntiles, per_xcd);
@@ -255,6 +273,16 @@ hipError_t stimulate_impl(Real* u, int64_t pitch, int nx, int ny, const Disks& d
 }
 
 template <typename Real>
+hipError_t copy_plane_impl(const Real* u, int64_t pitch, int nx, int ny, Real* tl,
+                           int64_t tpitch, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny;
+    const int64_t blocks = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+    hipLaunchKernelGGL((k_copy_plane<Real>), dim3((unsigned)blocks), dim3(256), 0, s, u, pitch,
+                       nx, ny, tl, tpitch);
+    return hipGetLastError();
+}
+
+template <typename Real>
 hipError_t arrival_init_impl(const Real* u, int64_t pitch, int nx, int ny, Real theta,
                              int32_t* arrival, int64_t apitch, int step, hipStream_t s) {
     const int64_t n = (int64_t)nx * ny;
@@ -272,7 +300,7 @@ hipError_t launch_step1(const StepArgs<double>& a, hipStream_t s) { return step1
 bool tile_rows_supported(int rows) {
     return rows == 48 || rows == 56 || rows == 64 || rows == 80;
 }
-int tile_rows_default() { return 80; }
+int tile_rows_default() { return 56; }
 
 hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s) {
     switch (rows) {
@@ -296,6 +324,14 @@ hipError_t launch_stimulate(double* u, int64_t pitch, int nx, int ny, const Disk
 hipError_t launch_arrival_init(const float* u, int64_t pitch, int nx, int ny, float theta,
                                int32_t* arrival, int64_t apitch, int step, hipStream_t s) {
     return arrival_init_impl(u, pitch, nx, ny, theta, arrival, apitch, step, s);
+}
+hipError_t launch_copy_plane(const float* u, int64_t pitch, int nx, int ny, float* tl,
+                             int64_t tpitch, hipStream_t s) {
+    return copy_plane_impl(u, pitch, nx, ny, tl, tpitch, s);
+}
+hipError_t launch_copy_plane(const double* u, int64_t pitch, int nx, int ny, double* tl,
+                             int64_t tpitch, hipStream_t s) {
+    return copy_plane_impl(u, pitch, nx, ny, tl, tpitch, s);
 }
 hipError_t launch_arrival_init(const double* u, int64_t pitch, int nx, int ny, double theta,
                                int32_t* arrival, int64_t apitch, int step, hipStream_t s) {

@@ -147,9 +147,10 @@ constexpr int kTileWaves = 8;
 // Two 8-wave workgroups per CU (4 waves per SIMD, a 128-VGPR budget) when
 // the tile's LDS allows it; the second launch-bounds argument is the minimum
 // number of waves per SIMD.
-// (The arrival-tracking variant keeps 4R more registers and is not held to it.)
-template <int R, bool ARR>
-constexpr int tile_waves_per_simd() { return (R <= 8 && !ARR) ? 4 : 2; }
+// (The output variant -- arrival map and/or timelapse -- keeps up to 8R more
+// registers and is not held to it.)
+template <int R, bool OUT>
+constexpr int tile_waves_per_simd() { return (R <= 8 && !OUT) ? 4 : 2; }
 
 // Output tile of k_stepT / the batched kernel: BX columns by BY rows.
 template <int T, int R>
@@ -163,7 +164,7 @@ struct TileGeom {
 // load the tile with its mirrored halo, run the sub-steps on chip, store the
 // interior.  Called by one 512-thread workgroup; `lds` is that workgroup's
 // tile of u.
-template <int T, int R, bool ARR>
+template <int T, int R, bool OUT>
 __device__ __forceinline__ void step_tile(const StepArgs<float>& a, int tx, int ty,
                                           float4 (&lds)[kTileWaves * R][64]) {
     constexpr int HX = (T + 3) & ~3;          // column halo, rounded to whole lanes
@@ -213,9 +214,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<float>& a, int tx, int 
     }
 
     // Output cells: rows [T, EY-T), lanes [HX/4, 64-HX/4), inside the grid.
+    // The output variant carries their arrival times and timelapse maxima
+    // through the sub-steps in registers.
     const bool out_lane = lane >= HX / 4 && lane < 64 - HX / 4;
-    int ar[ARR ? R : 1][4];
-    if (ARR) {
+    int ar[OUT ? R : 1][4];
+    float tm[OUT ? R : 1][4];
+    if (OUT) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int r = w + kTileWaves * k;
@@ -223,7 +227,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<float>& a, int tx, int 
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const bool in = out_lane && r >= T && r < EY - T && gy < ny && gx + c < nx;
-                ar[k][c] = in ? a.arrival[(int64_t)gy * a.apitch + gx + c] : 0;
+                ar[k][c] = in && a.arrival ? a.arrival[(int64_t)gy * a.apitch + gx + c] : 0;
+                tm[k][c] = in && a.tl ? a.tl[(int64_t)gy * a.tpitch + gx + c] : 0.0f;
             }
         }
     }
@@ -246,10 +251,17 @@ __device__ __forceinline__ void step_tile(const StepArgs<float>& a, int tx, int 
                 cell_update(c.y, c.x, c.z, n.y, s.y, vr[k][1], pr[k][1], a.k, un[k][1], vr[k][1]);
                 cell_update(c.z, c.y, c.w, n.z, s.z, vr[k][2], pr[k][2], a.k, un[k][2], vr[k][2]);
                 cell_update(c.w, c.z, east, n.w, s.w, vr[k][3], pr[k][3], a.k, un[k][3], vr[k][3]);
-                if (ARR && r >= T && r < EY - T) {
+                if (OUT && r >= T && r < EY - T) {
+                    if (a.arrival) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (ar[k][e] == kNever && un[k][e] >= a.theta) ar[k][e] = a.step0 + t;
+                        for (int e = 0; e < 4; ++e)
+                            if (ar[k][e] == kNever && un[k][e] >= a.theta) ar[k][e] = a.step0 + t;
+                    }
+                    if (a.tl && (a.step0 + t) % a.tl_rate == 0) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (un[k][e] > tm[k][e]) tm[k][e] = un[k][e];
+                    }
                 }
             }
         }
@@ -291,10 +303,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<float>& a, int tx, int 
                     }
                 }
             }
-            if (ARR) {
+            if (OUT && a.arrival) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     if (gx + c < nx) a.arrival[(int64_t)gy * a.apitch + gx + c] = ar[k][c];
+            }
+            if (OUT && a.tl) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (gx + c < nx) a.tl[(int64_t)gy * a.tpitch + gx + c] = tm[k][c];
             }
         }
     }

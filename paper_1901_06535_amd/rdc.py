@@ -27,8 +27,8 @@ NEVER = 0x7FFFFFFF
 # Every symbol include/rdc.h declares.
 EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_write",
            "rdc_stimulate", "rdc_step", "rdc_read", "rdc_set_block", "rdc_set_tile_rows",
-           "rdc_tile_rows_supported", "rdc_current", "rdc_set_arrival", "rdc_get_step",
-           "rdc_last_error", "rdc_copy", "rdc_status_string",
+           "rdc_tile_rows_supported", "rdc_current", "rdc_set_arrival", "rdc_set_timelapse",
+           "rdc_get_step", "rdc_last_error", "rdc_copy", "rdc_status_string",
            "rdc_batch_create", "rdc_batch_destroy", "rdc_batch_set_block", "rdc_batch_set_phi",
            "rdc_batch_write", "rdc_batch_stimulate", "rdc_batch_step", "rdc_batch_read",
            "rdc_batch_capture", "rdc_graph_launch", "rdc_graph_destroy", "rdc_batch_last_error",
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_tile_rows_supported": (i32, [i32]),
         "rdc_current": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "rdc_set_arrival": (i32, [vp, vp, i64, ctypes.c_double]),
+        "rdc_set_timelapse": (i32, [vp, vp, i64, i32]),
         "rdc_get_step": (i32, [vp, ctypes.POINTER(i64)]),
         "rdc_last_error": (ctypes.c_char_p, [vp]),
         "rdc_copy": (i32, [vp, vp, i64, vp]),
@@ -219,6 +220,10 @@ def rdc_set_arrival(ctx, ptr: Optional[int], pitch: int, theta: float) -> None:
     _check(load().rdc_set_arrival(ctx, ptr, pitch, theta), ctx)
 
 
+def rdc_set_timelapse(ctx, ptr: Optional[int], pitch: int, rate: int) -> None:
+    _check(load().rdc_set_timelapse(ctx, ptr, pitch, rate), ctx)
+
+
 def rdc_get_step(ctx) -> int:
     s = ctypes.c_int64()
     _check(load().rdc_get_step(ctx, ctypes.byref(s)), ctx)
@@ -271,6 +276,7 @@ class Sim:
             self.ctx = rdc_create(self.nx, self.ny, RDC_FP64 if dtype == "fp64" else RDC_FP32, b,
                                   self.stream.cuda_stream)
         self.arrival_plane = None
+        self.params = None
         if params is not None:
             self.set_params(params)
 
@@ -278,6 +284,7 @@ class Sim:
     def set_params(self, params) -> None:
         p = rdc_params(*(float(params[k]) for k in ("eps", "f", "q", "D_u", "dt", "dx")))
         rdc_set_params(self.ctx, p)
+        self.params = dict(params)
 
     def _host(self, a) -> np.ndarray:
         a = np.ascontiguousarray(a, dtype=self.np_dtype)
@@ -315,6 +322,12 @@ class Sim:
 
     def set_tile_rows(self, rows: int) -> None:
         rdc_set_tile_rows(self.ctx, rows)
+
+    def autotune(self, **kw):
+        """Time the launch shapes on this grid's shape (cached) and use the
+        fastest; see autotune.tune_sim."""
+        from . import autotune
+        return autotune.tune_sim(self, **kw)
 
     def step(self, n: int) -> None:
         rdc_step(self.ctx, n)
@@ -364,6 +377,18 @@ class Sim:
         self.stream.synchronize()
         return self.arrival_plane[:, : self.nx].cpu().numpy()
 
+    def enable_timelapse(self, rate: int) -> None:
+        """Record the max of u over frames taken every `rate` steps (the
+        current state is the first frame); see rdc_set_timelapse."""
+        t = self._torch
+        self.timelapse_plane = t.empty((self.ny, self.pitch), dtype=self.tdtype,
+                                       device=self.device)
+        rdc_set_timelapse(self.ctx, self.timelapse_plane.data_ptr(), self.pitch, rate)
+
+    def timelapse(self) -> np.ndarray:
+        self.stream.synchronize()
+        return self.timelapse_plane[:, : self.nx].cpu().numpy()
+
     def synchronize(self) -> None:
         self.stream.synchronize()
 
@@ -403,6 +428,7 @@ class BatchSim:
             raise RuntimeError("no GPU visible: the stepper runs only on the HIP device")
         lib = load()
         self.count = len(specs)
+        self.specs = [(int(nx), int(ny), dict(p)) for nx, ny, p in specs]
         self.device = torch.device(device if device is not None else "cuda")
         descs = (rdc_sim_desc * self.count)()
         self.shapes = []
@@ -438,6 +464,12 @@ class BatchSim:
 
     def set_block(self, T: int, rows: int = 56) -> None:
         _bcheck(load().rdc_batch_set_block(self.b, T, rows), self.b)
+
+    def autotune(self, **kw):
+        """Time the launch shapes on these grids' shapes (cached) and use the
+        fastest; see autotune.tune_batch."""
+        from . import autotune
+        return autotune.tune_batch(self, **kw)
 
     def set_phi(self, i: int, phi) -> None:
         a = self._host(i, phi)

@@ -462,6 +462,11 @@ class CoarseStepper:
         for s in (self.sim, self.judge, self.ref):
             if s is not None:
                 s.set_phi(phi)
+        shape = self.sim.autotune()
+        for s in (self.judge, self.ref):
+            if s is not None:
+                s.set_block(shape["T"])
+                s.set_tile_rows(shape["rows"])
         self.nx, self.ny, self.pitch = nx, ny, self.sim.pitch
         self.plane = ny * self.pitch
         self.ws = Workspace(net, 1, ny, nx, train=False)

@@ -337,6 +337,33 @@ def test_inhibitory_background_settles_on_period_two_orbit():
     assert min(seq) < us < max(seq)
 
 
+# ---------------------------------------------------------------- timelapse
+
+@pytest.mark.parametrize("rate,chunks", [(1, [7, 5]), (3, [1, 1, 10, 4]), (7, [20, 2])])
+def test_timelapse_is_the_max_over_frames_every_rate_steps(rate, chunks):
+    """Run.track_timelapse against a step-by-step record of every frame: the
+    first frame is the state at attach time, then one frame after each step
+    that leaves an index divisible by rate, however advance() is split."""
+    u, v, phi = inputs.random_state(23, 17, seed=9)
+    run = oracle.Run(u, v, phi, P)
+    run.stimulate([(11, 8, 3)])
+    run.advance(2)
+    run.track_timelapse(rate)
+    frames = [run.u.copy()]
+    uu, vv = run.u.copy(), run.v.copy()
+    t = run.step_index
+    for n in chunks:
+        run.advance(n)
+        for _ in range(n):
+            uu, vv = oracle.step(uu, vv, phi, P)
+            t += 1
+            if t % rate == 0:
+                frames.append(uu.copy())
+    assert np.array_equal(run.u, uu)
+    assert np.array_equal(run.timelapse, np.max(frames, axis=0))
+    assert len(frames) == 1 + (t // rate - 2 // rate)
+
+
 # ---------------------------------------------------------------- Euler pole bound
 
 def _one_cell_step(u, c, params):
