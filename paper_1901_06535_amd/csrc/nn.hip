@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <initializer_list>
+
 #include "nn.h"
 
 namespace rdc {
@@ -48,64 +50,145 @@ __device__ __forceinline__ bf16x8 zero8() {
 
 // ------------------------------------------------------------------ convolution
 
-// One wave: pixels x0..x0+31 of row y of image n, output channels
-// [0, 32*NB).  Grid: x = row segments / 4, y = N images; block = 4 waves,
-// each wave its own row segment.
-template <int NB, bool RELU, bool BIAS>
-__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int seg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int segs_per_row = a.W >> 5;
-    if (seg >= segs_per_row * a.H) return;
-    const int y = seg / segs_per_row;
-    const int x0 = (seg % segs_per_row) << 5;
-    const int n = blockIdx.y;
-    const int px = x0 + (lane & 31);          // this lane's pixel (B column, D column)
-    const int kq = (lane >> 5) << 3;          // this lane's 8-wide slice of the 16 K
-    const __bf16* X = a.x + (int64_t)n * a.H * a.W * a.ldx;
-    f32x16 acc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc[b][i] = 0.0f;
+// Convolution tile: a workgroup of kConvWaves waves computes kConvWaves
+// output rows (one per wave) x 32*P columns x all cout channels (NB
+// accumulator blocks of 32).  The input tile with its one-pixel halo
+// (kConvWaves + 2 rows x (32P + 2) columns) is
+// staged through LDS 32 input channels at a time, each pixel padded to 40
+// channels (80 bytes) so a lane's 8-channel B operand is one aligned 16-byte
+// LDS read; every staged element serves all nine taps.  Weights (A operand)
+// come from global memory -- every workgroup reads the same ones, so they hit
+// L1/L2 -- once per (tap, K-step, channel block) and serve the P pixel blocks.
+// Input channels past cin (cin % 32 == 16) are staged as zeros and their
+// weights read as zeros.
+#ifndef RDC_CONV_WAVES
+#define RDC_CONV_WAVES 4        // output rows (one per wave) per workgroup
+#endif
+constexpr int kConvWaves = RDC_CONV_WAVES;
+constexpr int kConvKc = 32;     // input channels per LDS stage
+constexpr int kConvPix = 40;    // LDS elements per staged pixel (32 + 8 padding)
 
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1;
-        const int xx = px + tap % 3 - 1;
-        const bool in = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-        const __bf16* xp = X + ((int64_t)(in ? yy : 0) * a.W + (in ? xx : 0)) * a.ldx + kq;
-        const __bf16* wp = a.w + (int64_t)tap * a.cout * a.cin + (int64_t)(lane & 31) * a.cin + kq;
-        for (int c0 = 0; c0 < a.cin; c0 += 16) {
-            const bf16x8 bx = in ? load8(xp + c0) : zero8();
+#ifndef RDC_CONV_P_NB1
+#define RDC_CONV_P_NB1 4        // pixel blocks per wave when cout = 32
+#endif
+#ifndef RDC_CONV_P_NB2
+#define RDC_CONV_P_NB2 2        // ... when cout = 64 (and 96, 128)
+#endif
+
+template <int NB>
+constexpr int conv_pixel_blocks() {
+    return NB == 1 ? RDC_CONV_P_NB1 : (NB <= 4 ? RDC_CONV_P_NB2 : 1);
+}
+
+template <int NB, int P, bool RELU, bool BIAS>
+__global__ __launch_bounds__(kConvWaves * 64) void k_conv3x3(ConvArgs a) {
+    constexpr int CT = 32 * P + 2;             // staged columns
+    constexpr int RT = kConvWaves + 2;         // staged rows
+    __shared__ __attribute__((aligned(16))) __bf16 tile[RT * CT * kConvPix];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int x0 = blockIdx.x * 32 * P;
+    const int y0 = blockIdx.y * kConvWaves;
+    const int n = blockIdx.z;
+    const int y = y0 + wv;
+    const __bf16* X = a.x + (int64_t)n * a.H * a.W * a.ldx;
+    const int kq = (lane >> 5) << 3;           // this lane's 8-wide slice of a 16-K step
+    const int pl = lane & 31;                  // this lane's pixel in a block (B / D column)
+    f32x16 acc[P][NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const bf16x8 aw = load8(wp + (int64_t)b * 32 * a.cin + c0);
-                acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, bx, acc[b], 0, 0, 0);
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[p][b][i] = 0.0f;
+
+    // Staging: thread t moves 16-byte pieces t, t + 256, ... of the tile
+    // (piece = 8 channels of one pixel); all of a thread's loads are issued
+    // before any LDS store, and the next chunk's loads are in flight while
+    // the current chunk is multiplied.
+    constexpr int kPieces = RT * CT * 4;
+    constexpr int kPer = (kPieces + kConvWaves * 64 - 1) / (kConvWaves * 64);
+    bf16x8 stage[kPer];
+    auto fetch = [&](int c0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = threadIdx.x + k * kConvWaves * 64;
+            const int q = i & 3;
+            const int pc = i >> 2;
+            const int r = pc / CT, c = pc - (pc / CT) * CT;
+            const int yy = y0 - 1 + r, xx = x0 - 1 + c;
+            const int ch = c0 + 8 * q;
+            stage[k] = (i < kPieces && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && ch < a.cin)
+                           ? load8(X + ((int64_t)yy * a.W + xx) * a.ldx + ch)
+                           : zero8();
+        }
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < a.cin; c0 += kConvKc) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const int i = threadIdx.x + k * kConvWaves * 64;
+            if (i < kPieces)
+                *reinterpret_cast<bf16x8*>(&tile[(i >> 2) * kConvPix + 8 * (i & 3)]) = stage[k];
+        }
+        __syncthreads();
+        if (c0 + kConvKc < a.cin) fetch(c0 + kConvKc);
+        if (y < a.H) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int ty = tap / 3, tx = tap % 3;   // input = output + (ty - 1, tx - 1)
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const int ci = c0 + ks * 16 + kq;
+                    bf16x8 aw[NB];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        aw[b] = ci < a.cin
+                                    ? load8(a.w + ((int64_t)tap * a.cout + b * 32 + pl) * a.cin + ci)
+                                    : zero8();
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        if (x0 + p * 32 >= a.W) continue;          // uniform per wave
+                        const int col = p * 32 + pl + tx;
+                        const bf16x8 bx = *reinterpret_cast<const bf16x8*>(
+                            &tile[((wv + ty) * CT + col) * kConvPix + ks * 16 + kq]);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+                            acc[p][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[b], bx,
+                                                                                acc[p][b], 0, 0, 0);
+                    }
+                }
             }
         }
+        __syncthreads();
     }
-    // D[co, pixel]: lane holds pixel px and channels 8*(i/4) + 4*(lane/32) + i%4.
-    __bf16* Y = a.y + ((int64_t)n * a.H * a.W + (int64_t)y * a.W + px) * a.ldy;
+    if (y >= a.H) return;
+    // D[co, pixel]: lane holds pixel pl and channels 8*(i/4) + 4*(lane/32) + i%4.
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
+    for (int p = 0; p < P; ++p) {
+        if (x0 + p * 32 >= a.W) continue;
+        __bf16* Y = a.y + ((int64_t)n * a.H * a.W + (int64_t)y * a.W + x0 + p * 32 + pl) * a.ldy;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int co = b * 32 + g * 8 + ((lane >> 5) << 2);
-            __bf16 out[4];
+        for (int b = 0; b < NB; ++b) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                float t = acc[b][g * 4 + i];
-                if (BIAS) t += a.bias[co + i];
-                if (RELU) t = t > 0.0f ? t : 0.0f;
-                out[i] = f2bf(t);
-            }
-            if (co < a.cout_store) {
-                uint2 pk;
-                pk.x = (uint32_t)__builtin_bit_cast(uint16_t, out[0]) |
-                       ((uint32_t)__builtin_bit_cast(uint16_t, out[1]) << 16);
-                pk.y = (uint32_t)__builtin_bit_cast(uint16_t, out[2]) |
-                       ((uint32_t)__builtin_bit_cast(uint16_t, out[3]) << 16);
-                *reinterpret_cast<uint2*>(Y + co) = pk;
+            for (int g = 0; g < 4; ++g) {
+                const int co = b * 32 + g * 8 + ((lane >> 5) << 2);
+                __bf16 out[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float t = acc[p][b][g * 4 + i];
+                    if (BIAS) t += a.bias[co + i];
+                    if (RELU) t = t > 0.0f ? t : 0.0f;
+                    out[i] = f2bf(t);
+                }
+                if (co < a.cout_store) {
+                    uint2 pk;
+                    pk.x = (uint32_t)__builtin_bit_cast(uint16_t, out[0]) |
+                           ((uint32_t)__builtin_bit_cast(uint16_t, out[1]) << 16);
+                    pk.y = (uint32_t)__builtin_bit_cast(uint16_t, out[2]) |
+                           ((uint32_t)__builtin_bit_cast(uint16_t, out[3]) << 16);
+                    *reinterpret_cast<uint2*>(Y + co) = pk;
+                }
             }
         }
     }
@@ -331,6 +414,150 @@ __global__ void k_up2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int
     }
 }
 
+// 16-byte variants of the element-wise kernels above, used when the
+// channel count, the pixel strides and the base addresses allow 8-channel
+// (16-byte) accesses; item j = (pixel, 8-channel group), same arithmetic and
+// summation order as the scalar kernels.
+__device__ __forceinline__ void store8(__bf16* p, const bf16x8& v) {
+    *reinterpret_cast<bf16x8*>(p) = v;
+}
+
+__global__ void k_relu_bwd8(__bf16* g, int ldg, const __bf16* y, int ldy, int64_t pixels,
+                            int c8) {
+    const int64_t total = pixels * c8;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = j / c8;
+        const int q = (int)(j - p * c8) * 8;
+        const bf16x8 yv = load8(y + p * ldy + q);
+        bf16x8 gv = load8(g + p * ldg + q);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (!(bf2f(yv[e]) > 0.0f)) gv[e] = f2bf(0.0f);
+        store8(g + p * ldg + q, gv);
+    }
+}
+
+__global__ void k_pool2_8(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo,
+                          int c8) {
+    const int64_t total = (int64_t)N * Ho * Wo * c8;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = j / c8;
+        const int ch = (int)(j - q * c8) * 8;
+        const int x = q % Wo;
+        const int64_t r = q / Wo;
+        const int y = r % Ho;
+        const int n = r / Ho;
+        const int Wi = 2 * Wo;
+        const int64_t b = ((int64_t)n * 2 * Ho + 2 * y) * Wi + 2 * x;
+        const bf16x8 a0 = load8(in + b * ldi + ch), a1 = load8(in + (b + 1) * ldi + ch);
+        const bf16x8 a2 = load8(in + (b + Wi) * ldi + ch), a3 = load8(in + (b + Wi + 1) * ldi + ch);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            o[e] = f2bf(0.25f * (bf2f(a0[e]) + bf2f(a1[e]) + bf2f(a2[e]) + bf2f(a3[e])));
+        store8(out + q * ldo + ch, o);
+    }
+}
+
+__global__ void k_pool2_bwd8(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int Ho,
+                             int Wo, int c8, int accumulate) {
+    const int64_t total = (int64_t)N * Ho * Wo * c8;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = j / c8;
+        const int ch = (int)(j - q * c8) * 8;
+        const int x = q % Wo;
+        const int64_t r = q / Wo;
+        const int y = r % Ho;
+        const int n = r / Ho;
+        const int Wi = 2 * Wo;
+        const bf16x8 gv = load8(gout + q * ldo + ch);
+        float g[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) g[e] = 0.25f * bf2f(gv[e]);
+        const int64_t b = ((int64_t)n * 2 * Ho + 2 * y) * Wi + 2 * x;
+        const int64_t idx[4] = {b, b + 1, b + Wi, b + Wi + 1};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            __bf16* d = gin + idx[k] * ldi + ch;
+            bf16x8 o;
+            if (accumulate) {
+                const bf16x8 old = load8(d);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) o[e] = f2bf(bf2f(old[e]) + g[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) o[e] = f2bf(g[e]);
+            }
+            store8(d, o);
+        }
+    }
+}
+
+__global__ void k_up2_8(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo,
+                        int c8) {
+    const int64_t total = (int64_t)N * Ho * Wo * c8;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = j / c8;
+        const int ch = (int)(j - q * c8) * 8;
+        const int x = q % Wo;
+        const int64_t r = q / Wo;
+        const int y = r % Ho;
+        const int n = r / Ho;
+        const int64_t src = ((int64_t)n * (Ho / 2) + y / 2) * (Wo / 2) + x / 2;
+        store8(out + q * ldo + ch, load8(in + src * ldi + ch));
+    }
+}
+
+__global__ void k_up2_bwd8(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int Hi,
+                           int Wi, int c8) {
+    const int64_t total = (int64_t)N * Hi * Wi * c8;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = j / c8;
+        const int ch = (int)(j - q * c8) * 8;
+        const int x = q % Wi;
+        const int64_t r = q / Wi;
+        const int y = r % Hi;
+        const int n = r / Hi;
+        const int Wo = 2 * Wi;
+        const int64_t b = ((int64_t)n * 2 * Hi + 2 * y) * Wo + 2 * x;
+        const bf16x8 a0 = load8(gout + b * ldo + ch), a1 = load8(gout + (b + 1) * ldo + ch);
+        const bf16x8 a2 = load8(gout + (b + Wo) * ldo + ch);
+        const bf16x8 a3 = load8(gout + (b + Wo + 1) * ldo + ch);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            o[e] = f2bf(bf2f(a0[e]) + bf2f(a1[e]) + bf2f(a2[e]) + bf2f(a3[e]));
+        store8(gin + q * ldi + ch, o);
+    }
+}
+
+// Network input, one pixel per item, written as c/8 16-byte groups.
+__global__ void k_prep8(const float* u, const float* v, const float* phi, int64_t pitch,
+                        int64_t plane_stride, __bf16* x, int c8, int N, int H, int W, float su,
+                        float sv, float sp) {
+    const int64_t total = (int64_t)N * H * W;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int xx = j % W;
+        const int64_t r = j / W;
+        const int yy = r % H;
+        const int n = r / H;
+        const int64_t o = n * plane_stride + (int64_t)yy * pitch + xx;
+        bf16x8 first = zero8();
+        first[0] = f2bf(su * u[o]);
+        first[1] = f2bf(sv * v[o]);
+        first[2] = f2bf(sp * phi[o]);
+        __bf16* d = x + j * c8 * 8;
+        store8(d, first);
+        for (int k = 1; k < c8; ++k) store8(d + 8 * k, zero8());
+    }
+}
+
 // Network input from the stepper planes (fp32, row pitch `pitch`) of image n:
 // channels (u, v, phi) scaled by (su, sv, sp), the rest zero up to c.
 __global__ void k_prep(const float* u, const float* v, const float* phi, int64_t pitch,
@@ -482,9 +709,9 @@ inline unsigned grid_for(int64_t n, int block = 256) {
 
 template <int NB, bool RELU, bool BIAS>
 hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
-    const int segs = (a.W >> 5) * a.H;
-    const dim3 grid((segs + 3) / 4, a.N), block(256);
-    hipLaunchKernelGGL((k_conv3x3<NB, RELU, BIAS>), grid, block, 0, s, a);
+    constexpr int P = conv_pixel_blocks<NB>();
+    const dim3 grid((a.W + 32 * P - 1) / (32 * P), (a.H + kConvWaves - 1) / kConvWaves, a.N);
+    hipLaunchKernelGGL((k_conv3x3<NB, P, RELU, BIAS>), grid, dim3(kConvWaves * 64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -542,8 +769,23 @@ hipError_t conv3x3_wgrad(const WgradArgs& a, float* grad, float* gbias, hipStrea
     return hipGetLastError();
 }
 
+// 16-byte accesses possible for c channels at these strides and bases.
+inline bool vec8(int c, std::initializer_list<int> lds, std::initializer_list<const void*> ptrs) {
+    if (c % 8) return false;
+    for (int l : lds)
+        if (l % 8) return false;
+    for (const void* p : ptrs)
+        if (reinterpret_cast<uintptr_t>(p) & 15u) return false;
+    return true;
+}
+
 hipError_t relu_bwd(__bf16* g, int ldg, const __bf16* y, int ldy, int64_t pixels, int c,
                     hipStream_t s) {
+    if (vec8(c, {ldg, ldy}, {g, y})) {
+        hipLaunchKernelGGL(k_relu_bwd8, dim3(grid_for(pixels * (c / 8))), dim3(256), 0, s, g, ldg,
+                           y, ldy, pixels, c / 8);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_relu_bwd, dim3(grid_for(pixels * c)), dim3(256), 0, s, g, ldg, y, ldy,
                        pixels, c);
     return hipGetLastError();
@@ -551,6 +793,11 @@ hipError_t relu_bwd(__bf16* g, int ldg, const __bf16* y, int ldy, int64_t pixels
 
 hipError_t pool2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo, int c,
                  hipStream_t s) {
+    if (vec8(c, {ldi, ldo}, {in, out})) {
+        hipLaunchKernelGGL(k_pool2_8, dim3(grid_for((int64_t)N * Ho * Wo * (c / 8))), dim3(256), 0,
+                           s, in, ldi, out, ldo, N, Ho, Wo, c / 8);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_pool2, dim3(grid_for((int64_t)N * Ho * Wo * c)), dim3(256), 0, s, in,
                        ldi, out, ldo, N, Ho, Wo, c);
     return hipGetLastError();
@@ -558,6 +805,12 @@ hipError_t pool2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho,
 
 hipError_t pool2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int Ho, int Wo,
                      int c, bool accumulate, hipStream_t s) {
+    if (vec8(c, {ldo, ldi}, {gout, gin})) {
+        hipLaunchKernelGGL(k_pool2_bwd8, dim3(grid_for((int64_t)N * Ho * Wo * (c / 8))),
+                           dim3(256), 0, s, gout, ldo, gin, ldi, N, Ho, Wo, c / 8,
+                           accumulate ? 1 : 0);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_pool2_bwd, dim3(grid_for((int64_t)N * Ho * Wo * c)), dim3(256), 0, s,
                        gout, ldo, gin, ldi, N, Ho, Wo, c, accumulate ? 1 : 0);
     return hipGetLastError();
@@ -565,6 +818,11 @@ hipError_t pool2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, i
 
 hipError_t up2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, int Wo, int c,
                hipStream_t s) {
+    if (vec8(c, {ldi, ldo}, {in, out})) {
+        hipLaunchKernelGGL(k_up2_8, dim3(grid_for((int64_t)N * Ho * Wo * (c / 8))), dim3(256), 0,
+                           s, in, ldi, out, ldo, N, Ho, Wo, c / 8);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_up2, dim3(grid_for((int64_t)N * Ho * Wo * c)), dim3(256), 0, s, in, ldi,
                        out, ldo, N, Ho, Wo, c);
     return hipGetLastError();
@@ -572,6 +830,11 @@ hipError_t up2(const __bf16* in, int ldi, __bf16* out, int ldo, int N, int Ho, i
 
 hipError_t up2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int Hi, int Wi,
                    int c, hipStream_t s) {
+    if (vec8(c, {ldo, ldi}, {gout, gin})) {
+        hipLaunchKernelGGL(k_up2_bwd8, dim3(grid_for((int64_t)N * Hi * Wi * (c / 8))), dim3(256),
+                           0, s, gout, ldo, gin, ldi, N, Hi, Wi, c / 8);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_up2_bwd, dim3(grid_for((int64_t)N * Hi * Wi * c)), dim3(256), 0, s,
                        gout, ldo, gin, ldi, N, Hi, Wi, c);
     return hipGetLastError();
@@ -580,6 +843,11 @@ hipError_t up2_bwd(const __bf16* gout, int ldo, __bf16* gin, int ldi, int N, int
 hipError_t prep(const float* u, const float* v, const float* phi, int64_t pitch,
                 int64_t plane_stride, __bf16* x, int c, int N, int H, int W, float su, float sv,
                 float sp, hipStream_t s) {
+    if (c >= 8 && vec8(c, {}, {x})) {
+        hipLaunchKernelGGL(k_prep8, dim3(grid_for((int64_t)N * H * W)), dim3(256), 0, s, u, v, phi,
+                           pitch, plane_stride, x, c / 8, N, H, W, su, sv, sp);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_prep, dim3(grid_for((int64_t)N * H * W)), dim3(256), 0, s, u, v, phi,
                        pitch, plane_stride, x, c, N, H, W, su, sv, sp);
     return hipGetLastError();

@@ -35,7 +35,8 @@ rdc_status rdc_nn_conv3x3(const void* x, int32_t ldx, const void* w, const float
                           int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
                           int32_t cout, int32_t cout_store, int32_t relu, void* stream) {
     if (!x || !w || !y) return nfail("NULL tensor");
-    if (n < 1 || h < 1 || wd < 32 || wd % 32) return nfail("need n, h >= 1 and w a multiple of 32");
+    if (n < 1 || n > 65535 || h < 1 || h > 262140 || wd < 32 || wd % 32)
+        return nfail("need 1 <= n <= 65535, 1 <= h <= 262140 and w a multiple of 32");
     if (cin < 16 || cin % 16 || !(cout == 32 || cout == 64 || cout == 96 || cout == 128 ||
                                    cout == 192 || cout == 256))
         return nfail("need cin % 16 == 0, cout in {32, 64, 96, 128, 192, 256}");

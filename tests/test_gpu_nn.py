@@ -136,23 +136,26 @@ def test_wgrad_and_bias_grad(torch, cin, cout, N, H, W, ldx):
     assert (np.abs(gb.double().cpu().numpy() - rb) <= 2.0 ** -14 * mb).all()
 
 
-def test_relu_pool_upsample_and_adjoints(torch):
+@pytest.mark.parametrize("c,o_pool,o_acc,o_relu", [(48, 16, 8, 4), (48, 4, 12, 8), (44, 16, 8, 8)])
+def test_relu_pool_upsample_and_adjoints(torch, c, o_pool, o_acc, o_relu):
+    """Channel slices at 16-byte offsets and c % 8 == 0 take the 16-byte
+    kernels, the others the scalar ones; both must give the same values."""
     rng = np.random.default_rng(5)
-    N, H, W, c, ld = 2, 6, 64, 48, 64
+    N, H, W, ld = 2, 6, 64, 64
     s = _stream(torch)
     a, ar = _bf(torch, rng.standard_normal((N, H, W, ld)))
     # pool
     p = torch.zeros((N, H // 2, W // 2, c), dtype=torch.bfloat16, device="cuda")
-    rdc.nn("pool2", a.data_ptr() + 16 * 2, ld, p.data_ptr(), c, N, H // 2, W // 2, c, s)
-    ap = ar[..., 16:16 + c]
+    rdc.nn("pool2", a.data_ptr() + o_pool * 2, ld, p.data_ptr(), c, N, H // 2, W // 2, c, s)
+    ap = ar[..., o_pool:o_pool + c]
     pref = 0.25 * (ap[:, 0::2, 0::2] + ap[:, 0::2, 1::2] + ap[:, 1::2, 0::2] + ap[:, 1::2, 1::2])
     # pool adjoint, accumulating into a channel slice
     g, gr = _bf(torch, rng.standard_normal((N, H // 2, W // 2, c)))
     acc, accr = _bf(torch, rng.standard_normal((N, H, W, ld)))
-    rdc.nn("pool2_bwd", g.data_ptr(), c, acc.data_ptr() + 8 * 2, ld, N, H // 2, W // 2, c, 1, s)
+    rdc.nn("pool2_bwd", g.data_ptr(), c, acc.data_ptr() + o_acc * 2, ld, N, H // 2, W // 2, c, 1, s)
     up_g = np.repeat(np.repeat(gr, 2, axis=1), 2, axis=2)
     accref = accr.copy()
-    accref[..., 8:8 + c] += 0.25 * up_g
+    accref[..., o_acc:o_acc + c] += 0.25 * up_g
     # upsample and its adjoint
     u = torch.zeros((N, H, W, c), dtype=torch.bfloat16, device="cuda")
     rdc.nn("up2", g.data_ptr(), c, u.data_ptr(), c, N, H, W, c, s)
@@ -162,9 +165,11 @@ def test_relu_pool_upsample_and_adjoints(torch):
     # relu adjoint on a slice
     y, yr = _bf(torch, rng.standard_normal((N, H, W, ld)))
     gg, ggr = _bf(torch, rng.standard_normal((N, H, W, ld)))
-    rdc.nn("relu_bwd", gg.data_ptr() + 4 * 2, ld, y.data_ptr() + 4 * 2, ld, N * H * W, c, s)
+    rdc.nn("relu_bwd", gg.data_ptr() + o_relu * 2, ld, y.data_ptr() + o_relu * 2, ld, N * H * W,
+           c, s)
     rref = ggr.copy()
-    rref[..., 4:4 + c] = np.where(yr[..., 4:4 + c] > 0, ggr[..., 4:4 + c], 0.0)
+    rref[..., o_relu:o_relu + c] = np.where(yr[..., o_relu:o_relu + c] > 0,
+                                          ggr[..., o_relu:o_relu + c], 0.0)
     _sync(torch)
     for got, ref in ((p, pref), (acc, accref), (gu, guref)):
         assert (np.abs(_host(got) - ref) <= HALF_ULP * np.abs(ref)).all()
