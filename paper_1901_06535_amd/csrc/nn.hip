@@ -54,9 +54,10 @@ __device__ __forceinline__ bf16x8 zero8() {
 // output rows (one per wave) x 32*P columns x all cout channels (NB
 // accumulator blocks of 32).  The input tile with its one-pixel halo
 // (kConvWaves + 2 rows x (32P + 2) columns) is
-// staged through LDS 32 input channels at a time, each pixel padded to 40
-// channels (80 bytes) so a lane's 8-channel B operand is one aligned 16-byte
-// LDS read; every staged element serves all nine taps.  Weights (A operand)
+// staged through LDS 32 input channels at a time (64 bytes per pixel, its
+// four 16-byte slots swizzled against bank conflicts) so a lane's 8-channel
+// B operand is one aligned 16-byte LDS read; every staged element serves all
+// nine taps.  Weights (A operand)
 // come from global memory -- every workgroup reads the same ones, so they hit
 // L1/L2 -- once per (tap, K-step, channel block) and serve the P pixel blocks.
 // Input channels past cin (cin % 32 == 16) are staged as zeros and their
@@ -66,7 +67,12 @@ __device__ __forceinline__ bf16x8 zero8() {
 #endif
 constexpr int kConvWaves = RDC_CONV_WAVES;
 constexpr int kConvKc = 32;     // input channels per LDS stage
-constexpr int kConvPix = 40;    // LDS elements per staged pixel (32 + 8 padding)
+constexpr int kConvPix = 32;    // LDS elements per staged pixel
+
+// The four 16-byte slots of staged pixel p are permuted by XOR with
+// (p >> 1) & 3, so the 32 lanes reading one slot of 32 consecutive pixels
+// spread over the LDS banks.
+__device__ __forceinline__ int conv_slot(int pixel, int slot) { return slot ^ ((pixel >> 1) & 3); }
 
 #ifndef RDC_CONV_P_NB1
 #define RDC_CONV_P_NB1 4        // pixel blocks per wave when cout = 32
@@ -80,8 +86,10 @@ constexpr int conv_pixel_blocks() {
     return NB == 1 ? RDC_CONV_P_NB1 : (NB <= 4 ? RDC_CONV_P_NB2 : 1);
 }
 
+// Two waves per SIMD: with the loops below branch-free the compiler would
+// otherwise hoist every tap's operands and drop to one.
 template <int NB, int P, bool RELU, bool BIAS>
-__global__ __launch_bounds__(kConvWaves * 64) void k_conv3x3(ConvArgs a) {
+__global__ __launch_bounds__(kConvWaves * 64, 2) void k_conv3x3(ConvArgs a) {
     constexpr int CT = 32 * P + 2;             // staged columns
     constexpr int RT = kConvWaves + 2;         // staged rows
     __shared__ __attribute__((aligned(16))) __bf16 tile[RT * CT * kConvPix];
@@ -112,15 +120,19 @@ __global__ __launch_bounds__(kConvWaves * 64) void k_conv3x3(ConvArgs a) {
     auto fetch = [&](int c0) __attribute__((always_inline)) {
 #pragma unroll
         for (int k = 0; k < kPer; ++k) {
+            // Branch-free: out-of-range pieces load a clamped, valid address
+            // and are replaced by zeros.
             const int i = threadIdx.x + k * kConvWaves * 64;
             const int q = i & 3;
-            const int pc = i >> 2;
+            const int pc = min(i >> 2, RT * CT - 1);
             const int r = pc / CT, c = pc - (pc / CT) * CT;
             const int yy = y0 - 1 + r, xx = x0 - 1 + c;
             const int ch = c0 + 8 * q;
-            stage[k] = (i < kPieces && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && ch < a.cin)
-                           ? load8(X + ((int64_t)yy * a.W + xx) * a.ldx + ch)
-                           : zero8();
+            const bool ok = i < kPieces && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W &&
+                            ch < a.cin;
+            const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
+            const bf16x8 t = load8(X + ((int64_t)yc * a.W + xc) * a.ldx + (ch < a.cin ? ch : 0));
+            stage[k] = ok ? t : zero8();
         }
     };
     fetch(0);
@@ -129,7 +141,8 @@ __global__ __launch_bounds__(kConvWaves * 64) void k_conv3x3(ConvArgs a) {
         for (int k = 0; k < kPer; ++k) {
             const int i = threadIdx.x + k * kConvWaves * 64;
             if (i < kPieces)
-                *reinterpret_cast<bf16x8*>(&tile[(i >> 2) * kConvPix + 8 * (i & 3)]) = stage[k];
+                *reinterpret_cast<bf16x8*>(
+                    &tile[(i >> 2) * kConvPix + 8 * conv_slot(i >> 2, i & 3)]) = stage[k];
         }
         __syncthreads();
         if (c0 + kConvKc < a.cin) fetch(c0 + kConvKc);
@@ -140,18 +153,21 @@ __global__ __launch_bounds__(kConvWaves * 64) void k_conv3x3(ConvArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
                     const int ci = c0 + ks * 16 + kq;
+                    const bool ci_ok = ci < a.cin;
                     bf16x8 aw[NB];
 #pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        aw[b] = ci < a.cin
-                                    ? load8(a.w + ((int64_t)tap * a.cout + b * 32 + pl) * a.cin + ci)
-                                    : zero8();
+                    for (int b = 0; b < NB; ++b) {
+                        const bf16x8 t = load8(a.w + ((int64_t)tap * a.cout + b * 32 + pl) * a.cin +
+                                               (ci_ok ? ci : 0));
+                        aw[b] = ci_ok ? t : zero8();
+                    }
+                    // Pixel blocks past the image's right edge multiply the
+                    // zeros staged there and are not stored.
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        if (x0 + p * 32 >= a.W) continue;          // uniform per wave
-                        const int col = p * 32 + pl + tx;
+                        const int pix = (wv + ty) * CT + p * 32 + pl + tx;
                         const bf16x8 bx = *reinterpret_cast<const bf16x8*>(
-                            &tile[((wv + ty) * CT + col) * kConvPix + ks * 16 + kq]);
+                            &tile[pix * kConvPix + 8 * conv_slot(pix, 2 * ks + (kq >> 3))]);
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
                             acc[p][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[b], bx,
