@@ -350,13 +350,15 @@ rdc_status rdc_nn_apply(const float *u, const float *v, const float *phi, const 
                         int32_t n, int32_t h, int32_t w, float su, float sv, float f, float cmax,
                         void *stream);
 
-/* Blocks of per-block loss partials rdc_nn_loss writes for `pixels` pixels. */
+/* Number of per-block loss partials rdc_nn_loss writes for `pixels` pixels;
+ * `partial` must hold one float more (the total). */
 int32_t rdc_nn_loss_blocks(int64_t pixels);
 
 /* Front-weighted squared error of the head against the scaled increments
  * (su (ut - u), sv (vt - v)), weight 1 + front_w where u or ut crosses
  * theta, mean over pixels; writes its gradient into g (channels 0, 1; the
- * rest of ldg zero) and per-block partial sums into `partial`. */
+ * rest of ldg zero), per-block partial sums into partial[0 .. nb) and the
+ * loss (their sum, fixed order) into partial[nb], nb = rdc_nn_loss_blocks. */
 rdc_status rdc_nn_loss(const float *u, const float *v, const float *ut, const float *vt,
                        int64_t pitch, int64_t plane_stride, const void *head, int32_t ldh,
                        void *g, int32_t ldg, int32_t n, int32_t h, int32_t w, float su, float sv,

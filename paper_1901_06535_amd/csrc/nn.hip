@@ -50,163 +50,242 @@ __device__ __forceinline__ bf16x8 zero8() {
 
 // ------------------------------------------------------------------ convolution
 
-// Convolution tile: a workgroup of kConvWaves waves computes kConvWaves
-// output rows (one per wave) x 32*P columns x all cout channels (NB
-// accumulator blocks of 32).  The input tile with its one-pixel halo
-// (kConvWaves + 2 rows x (32P + 2) columns) is
-// staged through LDS 32 input channels at a time (64 bytes per pixel, its
-// four 16-byte slots swizzled against bank conflicts) so a lane's 8-channel
-// B operand is one aligned 16-byte LDS read; every staged element serves all
-// nine taps.  Weights (A operand)
-// come from global memory -- every workgroup reads the same ones, so they hit
-// L1/L2 -- once per (tap, K-step, channel block) and serve the P pixel blocks.
-// Input channels past cin (cin % 32 == 16) are staged as zeros and their
-// weights read as zeros.
-#ifndef RDC_CONV_WAVES
-#define RDC_CONV_WAVES 4        // output rows (one per wave) per workgroup
-#endif
-constexpr int kConvWaves = RDC_CONV_WAVES;
-constexpr int kConvKc = 32;     // input channels per LDS stage
-constexpr int kConvPix = 32;    // LDS elements per staged pixel
+// 3x3 "same" convolution as an implicit GEMM on v_mfma_f32_32x32x16_bf16
+// (D[co, pixel] += W[co, ci] X[ci, pixel] over 9 taps x cin), with memory
+// and matrix work in separate waves.  A 768-thread workgroup owns a strip of
+// 32*P output columns and sweeps a run of 8-row output tiles down it; the
+// work is a sequence of stages (tile, output-channel pass, 32-input-channel
+// chunk):
+//   * producer waves 8..11 stage the next stage into one of two LDS buffer
+//     pairs: the input tile with its one-pixel halo (10 rows x (32P + 2)
+//     columns x 32 channels, zeros outside the image and past cin) and the
+//     pass's weights (9 taps x 32*NBP output x 32 input channels);
+//   * consumer waves 0..7 (one output row each, two per SIMD) multiply the
+//     current stage from LDS only: per tap and 16-channel K step, A = 8 input
+//     channels of 32 output channels (one 16-byte read), reused over the P
+//     pixel blocks, B = 8 channels of the shifted input pixel (one 16-byte
+//     read), reused over the NBP channel blocks; after a pass's last chunk
+//     they add the bias, apply the ReLU and store NBP x 32 channels as bf16.
+// One barrier per stage hands the staged buffers over.  Producers and
+// consumers keep separate memory counters, so the consumers never wait on
+// global memory and the next stage's loads overlap the current multiplies.
+// LDS rows are 64 bytes (32 channels); the four 16-byte slots of row r are
+// permuted by XOR with (r >> 1) & 3 so 32 lanes reading one slot of 32
+// consecutive rows spread over the banks.
+constexpr int kConvRows = 8;                      // output rows per tile = consumer waves
+constexpr int kConvProducers = 4;                 // producer waves
+constexpr int kConvThreads = (kConvRows + kConvProducers) * 64;
+constexpr int kConvKc = 32;                       // input channels per stage
+constexpr int kConvPix = 32;                      // LDS elements per staged row
 
-// The four 16-byte slots of staged pixel p are permuted by XOR with
-// (p >> 1) & 3, so the 32 lanes reading one slot of 32 consecutive pixels
-// spread over the LDS banks.
-__device__ __forceinline__ int conv_slot(int pixel, int slot) { return slot ^ ((pixel >> 1) & 3); }
-
-#ifndef RDC_CONV_P_NB1
-#define RDC_CONV_P_NB1 4        // pixel blocks per wave when cout = 32
-#endif
-#ifndef RDC_CONV_P_NB2
-#define RDC_CONV_P_NB2 2        // ... when cout = 64 (and 96, 128)
+#ifndef RDC_CONV_WG_PER_CU
+#define RDC_CONV_WG_PER_CU 1    // workgroups launched per CU (each sweeps a run of tiles)
 #endif
 
+// Pixel blocks per consumer wave and output-channel blocks per pass; cout =
+// 32 NB = 32 NBP * passes.  The LDS budget (two stages of input and weights)
+// stays under 160 KB.
 template <int NB>
-constexpr int conv_pixel_blocks() {
-    return NB == 1 ? RDC_CONV_P_NB1 : (NB <= 4 ? RDC_CONV_P_NB2 : 1);
-}
+constexpr int conv_pixel_blocks() { return 2; }
+template <int NB>
+constexpr int conv_pass_blocks() { return NB % 2 == 0 ? 2 : 1; }
 
-// Two waves per SIMD: with the loops below branch-free the compiler would
-// otherwise hoist every tap's operands and drop to one.
-template <int NB, int P, bool RELU, bool BIAS>
-__global__ __launch_bounds__(kConvWaves * 64, 2) void k_conv3x3(ConvArgs a) {
-    constexpr int CT = 32 * P + 2;             // staged columns
-    constexpr int RT = kConvWaves + 2;         // staged rows
-    __shared__ __attribute__((aligned(16))) __bf16 tile[RT * CT * kConvPix];
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ int conv_slot(int row, int slot) { return slot ^ ((row >> 1) & 3); }
+
+template <int NBP, int PASSES, int P, bool RELU, bool BIAS>
+__global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_tiles, int runs,
+                                                          int run_len) {
+    constexpr int CT = 32 * P + 2;                       // staged columns
+    constexpr int RT = kConvRows + 2;                    // staged rows
+    constexpr int kXin = RT * CT * kConvPix;             // input elements per buffer
+    constexpr int kWrows = 9 * NBP * 32;                 // weight rows (tap, co) per stage
+    constexpr int kWts = kWrows * kConvPix;              // weight elements per buffer
+    constexpr int kPiecesX = RT * CT * 4;                // 16-byte pieces per stage
+    constexpr int kPiecesW = kWrows * 4;
+    constexpr int kPT = kConvProducers * 64;
+    constexpr int kPerX = (kPiecesX + kPT - 1) / kPT;
+    constexpr int kPerW = (kPiecesW + kPT - 1) / kPT;
+    __shared__ __attribute__((aligned(16))) __bf16 xin[2 * kXin];
+    __shared__ __attribute__((aligned(16))) __bf16 wts[2 * kWts];
+
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int x0 = blockIdx.x * 32 * P;
-    const int y0 = blockIdx.y * kConvWaves;
-    const int n = blockIdx.z;
-    const int y = y0 + wv;
-    const __bf16* X = a.x + (int64_t)n * a.H * a.W * a.ldx;
-    const int kq = (lane >> 5) << 3;           // this lane's 8-wide slice of a 16-K step
-    const int pl = lane & 31;                  // this lane's pixel in a block (B / D column)
-    f32x16 acc[P][NB];
+    const bool producer = wv >= kConvRows;
+    const int lane = threadIdx.x & 63;
+    const int x0 = (blockIdx.x / runs) * 32 * P;         // this strip's first column
+    const int total_tiles = a.N * row_tiles;
+    const int t_begin = (blockIdx.x % runs) * run_len;
+    const int t_end = min(t_begin + run_len, total_tiles);
+    const int chunks = (a.cin + kConvKc - 1) / kConvKc;
+    const int per_tile = PASSES * chunks;                // stages per tile
+    const int stages = (t_end - t_begin) * per_tile;
+
+    // Producer: stage s into buffers (s & 1), the input tile then the
+    // weights, each as one batch of loads followed by its LDS stores;
+    // out-of-range pieces load a clamped address and store 0.
+    auto produce = [&](int s) __attribute__((always_inline)) {
+        const int t = t_begin + s / per_tile;
+        const int pass = (s % per_tile) / chunks;
+        const int c0 = (s % chunks) * kConvKc;
+        const int n = t / row_tiles;
+        const int y0 = (t % row_tiles) * kConvRows;
+        const __bf16* X = a.x + (int64_t)n * a.H * a.W * a.ldx;
+        const int tid = threadIdx.x - kConvRows * 64;
+        __bf16* bx = xin + (s & 1) * kXin;
+        __bf16* bw = wts + (s & 1) * kWts;
+        {   // input tile: all loads, then all stores
+            bf16x8 vx[kPerX];
+#pragma unroll
+            for (int k = 0; k < kPerX; ++k) {
+                const int i = tid + k * kPT;
+                const int q = i & 3;
+                const int pc = min(i >> 2, RT * CT - 1);
+                const int r = pc / CT, c = pc - (pc / CT) * CT;
+                const int yy = y0 - 1 + r, xx = x0 - 1 + c;
+                const int ch = c0 + 8 * q;
+                const bool ok = i < kPiecesX && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W &&
+                                ch < a.cin;
+                const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
+                const bf16x8 ld =
+                    load8(X + ((int64_t)yc * a.W + xc) * a.ldx + (ch < a.cin ? ch : 0));
+                vx[k] = ok ? ld : zero8();
+            }
+#pragma unroll
+            for (int k = 0; k < kPerX; ++k) {
+                const int i = tid + k * kPT;
+                if (i < kPiecesX)
+                    *reinterpret_cast<bf16x8*>(
+                        &bx[(i >> 2) * kConvPix + 8 * conv_slot(i >> 2, i & 3)]) = vx[k];
+            }
+        }
+        {   // the pass's weights for this chunk
+            bf16x8 vw[kPerW];
+#pragma unroll
+            for (int k = 0; k < kPerW; ++k) {
+                const int i = tid + k * kPT;
+                const int q = i & 3;
+                const int row = min(i >> 2, kWrows - 1);      // (tap, co within the pass)
+                const int tap = row / (NBP * 32), co = pass * NBP * 32 + row % (NBP * 32);
+                const int ch = c0 + 8 * q;
+                const bool ok = i < kPiecesW && ch < a.cin;
+                const bf16x8 ld =
+                    load8(a.w + ((int64_t)tap * a.cout + co) * a.cin + (ch < a.cin ? ch : 0));
+                vw[k] = ok ? ld : zero8();
+            }
+#pragma unroll
+            for (int k = 0; k < kPerW; ++k) {
+                const int i = tid + k * kPT;
+                if (i < kPiecesW)
+                    *reinterpret_cast<bf16x8*>(
+                        &bw[(i >> 2) * kConvPix + 8 * conv_slot(i >> 2, i & 3)]) = vw[k];
+            }
+        }
+    };
+
+    // Producers and consumers run separate loops with the same number of
+    // workgroup barriers (the role is uniform per wave), so the consumers'
+    // accumulators are not live in the producers' code.
+    if (producer) {
+        if (stages > 0) produce(0);
+        __syncthreads();
+        for (int s = 0; s < stages; ++s) {
+            if (s + 1 < stages) produce(s + 1);
+            __syncthreads();
+        }
+        return;
+    }
+
+    const int kq = (lane >> 5) << 3;                 // this lane's 8-wide slice of a 16-K step
+    const int pl = lane & 31;                        // this lane's pixel / output row in a block
+    f32x16 acc[P][NBP];
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NBP; ++b)
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[p][b][i] = 0.0f;
 
-    // Staging: thread t moves 16-byte pieces t, t + 256, ... of the tile
-    // (piece = 8 channels of one pixel); all of a thread's loads are issued
-    // before any LDS store, and the next chunk's loads are in flight while
-    // the current chunk is multiplied.
-    constexpr int kPieces = RT * CT * 4;
-    constexpr int kPer = (kPieces + kConvWaves * 64 - 1) / (kConvWaves * 64);
-    bf16x8 stage[kPer];
-    auto fetch = [&](int c0) __attribute__((always_inline)) {
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            // Branch-free: out-of-range pieces load a clamped, valid address
-            // and are replaced by zeros.
-            const int i = threadIdx.x + k * kConvWaves * 64;
-            const int q = i & 3;
-            const int pc = min(i >> 2, RT * CT - 1);
-            const int r = pc / CT, c = pc - (pc / CT) * CT;
-            const int yy = y0 - 1 + r, xx = x0 - 1 + c;
-            const int ch = c0 + 8 * q;
-            const bool ok = i < kPieces && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W &&
-                            ch < a.cin;
-            const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
-            const bf16x8 t = load8(X + ((int64_t)yc * a.W + xc) * a.ldx + (ch < a.cin ? ch : 0));
-            stage[k] = ok ? t : zero8();
-        }
-    };
-    fetch(0);
-    for (int c0 = 0; c0 < a.cin; c0 += kConvKc) {
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            const int i = threadIdx.x + k * kConvWaves * 64;
-            if (i < kPieces)
-                *reinterpret_cast<bf16x8*>(
-                    &tile[(i >> 2) * kConvPix + 8 * conv_slot(i >> 2, i & 3)]) = stage[k];
-        }
-        __syncthreads();
-        if (c0 + kConvKc < a.cin) fetch(c0 + kConvKc);
-        if (y < a.H) {
-#pragma unroll
+    __syncthreads();
+    for (int s = 0; s < stages; ++s) {
+        {
+            const __bf16* bx = xin + (s & 1) * kXin;
+            const __bf16* bw = wts + (s & 1) * kWts;
+            // Taps unrolled in groups small enough to keep the operands of
+            // the taps in flight within the register budget of 3 waves/SIMD.
+            constexpr int kTapUnroll = NBP == 1 ? 3 : 1;
+#pragma unroll kTapUnroll
             for (int tap = 0; tap < 9; ++tap) {
                 const int ty = tap / 3, tx = tap % 3;   // input = output + (ty - 1, tx - 1)
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
-                    const int ci = c0 + ks * 16 + kq;
-                    const bool ci_ok = ci < a.cin;
-                    bf16x8 aw[NB];
+                    const int slot = 2 * ks + (kq >> 3);
+                    bf16x8 aw[NBP];
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        const bf16x8 t = load8(a.w + ((int64_t)tap * a.cout + b * 32 + pl) * a.cin +
-                                               (ci_ok ? ci : 0));
-                        aw[b] = ci_ok ? t : zero8();
+                    for (int b = 0; b < NBP; ++b) {
+                        const int row = tap * NBP * 32 + b * 32 + pl;
+                        aw[b] = *reinterpret_cast<const bf16x8*>(
+                            &bw[row * kConvPix + 8 * conv_slot(row, slot)]);
                     }
                     // Pixel blocks past the image's right edge multiply the
                     // zeros staged there and are not stored.
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const int pix = (wv + ty) * CT + p * 32 + pl + tx;
-                        const bf16x8 bx = *reinterpret_cast<const bf16x8*>(
-                            &tile[pix * kConvPix + 8 * conv_slot(pix, 2 * ks + (kq >> 3))]);
+                        const bf16x8 xv = *reinterpret_cast<const bf16x8*>(
+                            &bx[pix * kConvPix + 8 * conv_slot(pix, slot)]);
 #pragma unroll
-                        for (int b = 0; b < NB; ++b)
-                            acc[p][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[b], bx,
+                        for (int b = 0; b < NBP; ++b)
+                            acc[p][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw[b], xv,
                                                                                 acc[p][b], 0, 0, 0);
                     }
                 }
             }
-        }
-        __syncthreads();
-    }
-    if (y >= a.H) return;
-    // D[co, pixel]: lane holds pixel pl and channels 8*(i/4) + 4*(lane/32) + i%4.
+            const int c0 = (s % chunks) * kConvKc;
+            if (c0 + kConvKc >= a.cin) {                    // the pass's last chunk: store
+                const int t = t_begin + s / per_tile;
+                const int cb0 = ((s % per_tile) / chunks) * NBP * 32;
+                const int n = t / row_tiles;
+                const int y = (t % row_tiles) * kConvRows + wv;
+                if (y < a.H) {
+                    // D[co, pixel]: lane holds pixel pl, channels 8*(i/4) + 4*(lane/32) + i%4.
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        if (x0 + p * 32 >= a.W) continue;
-        __bf16* Y = a.y + ((int64_t)n * a.H * a.W + (int64_t)y * a.W + x0 + p * 32 + pl) * a.ldy;
+                    for (int p = 0; p < P; ++p) {
+                        if (x0 + p * 32 >= a.W) continue;
+                        __bf16* Y = a.y + ((int64_t)n * a.H * a.W + (int64_t)y * a.W + x0 + p * 32 +
+                                           pl) * a.ldy;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
+                        for (int b = 0; b < NBP; ++b) {
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int co = b * 32 + g * 8 + ((lane >> 5) << 2);
-                __bf16 out[4];
+                            for (int g = 0; g < 4; ++g) {
+                                const int co = cb0 + b * 32 + g * 8 + ((lane >> 5) << 2);
+                                __bf16 out[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    float t = acc[p][b][g * 4 + i];
-                    if (BIAS) t += a.bias[co + i];
-                    if (RELU) t = t > 0.0f ? t : 0.0f;
-                    out[i] = f2bf(t);
+                                for (int i = 0; i < 4; ++i) {
+                                    float v = acc[p][b][g * 4 + i];
+                                    if (BIAS) v += a.bias[co + i];
+                                    if (RELU) v = v > 0.0f ? v : 0.0f;
+                                    out[i] = f2bf(v);
+                                }
+                                if (co < a.cout_store) {
+                                    uint2 pk;
+                                    pk.x = (uint32_t)__builtin_bit_cast(uint16_t, out[0]) |
+                                           ((uint32_t)__builtin_bit_cast(uint16_t, out[1]) << 16);
+                                    pk.y = (uint32_t)__builtin_bit_cast(uint16_t, out[2]) |
+                                           ((uint32_t)__builtin_bit_cast(uint16_t, out[3]) << 16);
+                                    *reinterpret_cast<uint2*>(Y + co) = pk;
+                                }
+                            }
+                        }
+                    }
                 }
-                if (co < a.cout_store) {
-                    uint2 pk;
-                    pk.x = (uint32_t)__builtin_bit_cast(uint16_t, out[0]) |
-                           ((uint32_t)__builtin_bit_cast(uint16_t, out[1]) << 16);
-                    pk.y = (uint32_t)__builtin_bit_cast(uint16_t, out[2]) |
-                           ((uint32_t)__builtin_bit_cast(uint16_t, out[3]) << 16);
-                    *reinterpret_cast<uint2*>(Y + co) = pk;
-                }
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+#pragma unroll
+                    for (int b = 0; b < NBP; ++b)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) acc[p][b][i] = 0.0f;
             }
         }
+        __syncthreads();
     }
 }
 
@@ -726,8 +805,27 @@ inline unsigned grid_for(int64_t n, int block = 256) {
 template <int NB, bool RELU, bool BIAS>
 hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
     constexpr int P = conv_pixel_blocks<NB>();
-    const dim3 grid((a.W + 32 * P - 1) / (32 * P), (a.H + kConvWaves - 1) / kConvWaves, a.N);
-    hipLaunchKernelGGL((k_conv3x3<NB, P, RELU, BIAS>), grid, dim3(kConvWaves * 64), 0, s, a);
+    constexpr int NBP = conv_pass_blocks<NB>();
+    const int strips = (a.W + 32 * P - 1) / (32 * P);
+    const int row_tiles = (a.H + kConvRows - 1) / kConvRows;
+    const int total_tiles = a.N * row_tiles;
+    // Enough workgroups to fill the chip, each sweeping a contiguous run of
+    // row tiles of its strip (consecutive tiles share two staged rows in L2).
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            c > 0)
+            cus = c;
+    }
+    const int want = RDC_CONV_WG_PER_CU * cus;
+    int runs = (want + strips - 1) / strips;
+    runs = runs < 1 ? 1 : (runs > total_tiles ? total_tiles : runs);
+    const int run_len = (total_tiles + runs - 1) / runs;
+    runs = (total_tiles + run_len - 1) / run_len;
+    hipLaunchKernelGGL((k_conv3x3<NBP, NB / NBP, P, RELU, BIAS>), dim3(strips * runs),
+                       dim3(kConvThreads), 0, s, a, row_tiles, runs, run_len);
     return hipGetLastError();
 }
 
@@ -884,8 +982,14 @@ hipError_t loss(const float* u, const float* v, const float* ut, const float* vt
                 int H, int W, float su, float sv, float theta, float front_w, float* partial,
                 hipStream_t s) {
     const int64_t px = (int64_t)N * H * W;
-    hipLaunchKernelGGL(k_loss, dim3(loss_blocks(px)), dim3(256), 0, s, u, v, ut, vt, pitch,
-                       plane_stride, head, ldh, g, ldg, N, H, W, su, sv, theta, front_w, partial);
+    const int nb = loss_blocks(px);
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, u, v, ut, vt, pitch, plane_stride, head,
+                       ldh, g, ldg, N, H, W, su, sv, theta, front_w, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // The loss itself: the block partials summed in a fixed order into partial[nb].
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, s, partial, partial + nb, nb,
+                       (int64_t)1);
     return hipGetLastError();
 }
 

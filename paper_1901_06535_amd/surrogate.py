@@ -157,7 +157,7 @@ class Workspace:
             need = max(rdc.load().rdc_nn_wgrad_scratch_floats(N, *self._hw(name), cin, cout)
                        for name, cin, cout, _ in LAYERS)
             self.scratch = torch.empty(int(need), dtype=torch.float32, device=net.device)
-            self.partial = torch.empty(rdc.load().rdc_nn_loss_blocks(N * H * W),
+            self.partial = torch.empty(rdc.load().rdc_nn_loss_blocks(N * H * W) + 1,
                                        dtype=torch.float32, device=net.device)
 
     def _hw(self, name):
@@ -302,7 +302,7 @@ def loss_and_grad(net: UNet, ws: Workspace, u, v, ut, vt, pitch, plane_stride,
     rdc.nn("loss", u, v, ut, vt, pitch, plane_stride, _ptr(ws.a["head"]), HEAD_C,
            _ptr(ws.g["head"]), HEAD_C, ws.N, ws.H, ws.W, SU, SV, THETA, front_w,
            _ptr(ws.partial), net.stream.cuda_stream)
-    return float(ws.partial.sum().item())
+    return float(ws.partial[-1].item())
 
 
 def euler_safe_c(params, margin: float = 0.1) -> float:

@@ -210,7 +210,7 @@ def test_prep_apply_loss(torch):
            pitch, plane, uo.data_ptr(), vo.data_ptr(), N, H, W, su, sv, f, cmax, s)
     g = torch.full((N, H, W, 32), 9.0, dtype=torch.bfloat16, device="cuda")
     nb = rdc.load().rdc_nn_loss_blocks(N * H * W)
-    part = torch.zeros(nb, dtype=torch.float32, device="cuda")
+    part = torch.zeros(nb + 1, dtype=torch.float32, device="cuda")
     rdc.nn("loss", d["u"].data_ptr(), d["v"].data_ptr(), d["ut"].data_ptr(), d["vt"].data_ptr(),
            pitch, plane, head.data_ptr(), 32, g.data_ptr(), 32, N, H, W, su, sv, theta, fw,
            part.data_ptr(), s)
@@ -235,7 +235,8 @@ def test_prep_apply_loss(torch):
     L = unet_ref.loss(ht, c(u), c(v), c(ut), c(vt), su, sv, theta, fw)
     L.backward()
     L = float(L.detach())
-    assert abs(float(part.double().sum()) - L) <= 1e-5 * L
+    assert abs(float(part[:nb].double().sum()) - L) <= 1e-5 * L
+    assert abs(float(part[nb]) - L) <= 1e-5 * L          # the library's own total
     gref = ht.grad.numpy()
     gg = _host(g)
     assert (np.abs(gg[..., :2] - gref[..., :2]) <= HALF_ULP * np.abs(gref[..., :2]) +
