@@ -119,9 +119,9 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
     const int per_tile = PASSES * chunks;                // stages per tile
     const int stages = (t_end - t_begin) * per_tile;
 
-    // Producer: stage s into buffers (s & 1), the input tile then the
-    // weights, each as one batch of loads followed by its LDS stores;
-    // out-of-range pieces load a clamped address and store 0.
+    // Producer: stage s into buffers (s & 1): the input tile's loads, then
+    // its LDS stores, and the weights' (only when they change); out-of-range
+    // pieces load a clamped address and store 0.
     auto produce = [&](int s) __attribute__((always_inline)) {
         const int t = t_begin + s / per_tile;
         const int pass = (s % per_tile) / chunks;
@@ -132,33 +132,12 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
         const int tid = threadIdx.x - kConvRows * 64;
         __bf16* bx = xin + (s & 1) * kXin;
         __bf16* bw = wts + (s & 1) * kWts;
-        {   // input tile: all loads, then all stores
-            bf16x8 vx[kPerX];
-#pragma unroll
-            for (int k = 0; k < kPerX; ++k) {
-                const int i = tid + k * kPT;
-                const int q = i & 3;
-                const int pc = min(i >> 2, RT * CT - 1);
-                const int r = pc / CT, c = pc - (pc / CT) * CT;
-                const int yy = y0 - 1 + r, xx = x0 - 1 + c;
-                const int ch = c0 + 8 * q;
-                const bool ok = i < kPiecesX && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W &&
-                                ch < a.cin;
-                const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
-                const bf16x8 ld =
-                    load8(X + ((int64_t)yc * a.W + xc) * a.ldx + (ch < a.cin ? ch : 0));
-                vx[k] = ok ? ld : zero8();
-            }
-#pragma unroll
-            for (int k = 0; k < kPerX; ++k) {
-                const int i = tid + k * kPT;
-                if (i < kPiecesX)
-                    *reinterpret_cast<bf16x8*>(
-                        &bx[(i >> 2) * kConvPix + 8 * conv_slot(i >> 2, i & 3)]) = vx[k];
-            }
-        }
-        {   // the pass's weights for this chunk
-            bf16x8 vw[kPerW];
+        // The weights depend only on (pass, chunk): with one stage per tile
+        // they are the same for every stage, and both buffers are filled by
+        // the first two stages.
+        const bool need_w = per_tile > 1 || s < 2;
+        bf16x8 vx[kPerX], vw[kPerW];
+        auto load_w = [&]() __attribute__((always_inline)) {
 #pragma unroll
             for (int k = 0; k < kPerW; ++k) {
                 const int i = tid + k * kPT;
@@ -171,6 +150,37 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
                     load8(a.w + ((int64_t)tap * a.cout + co) * a.cin + (ch < a.cin ? ch : 0));
                 vw[k] = ok ? ld : zero8();
             }
+        };
+#pragma unroll
+        for (int k = 0; k < kPerX; ++k) {
+            const int i = tid + k * kPT;
+            const int q = i & 3;
+            const int pc = min(i >> 2, RT * CT - 1);
+            const int r = pc / CT, c = pc - (pc / CT) * CT;
+            const int yy = y0 - 1 + r, xx = x0 - 1 + c;
+            const int ch = c0 + 8 * q;
+            const bool ok = i < kPiecesX && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W &&
+                            ch < a.cin;
+            const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
+            const bf16x8 ld = load8(X + ((int64_t)yc * a.W + xc) * a.ldx + (ch < a.cin ? ch : 0));
+            vx[k] = ok ? ld : zero8();
+        }
+        // One latency phase when the registers allow it (one channel block
+        // per pass); two otherwise.
+        if constexpr (NBP == 1) {
+            if (need_w) load_w();
+        }
+#pragma unroll
+        for (int k = 0; k < kPerX; ++k) {
+            const int i = tid + k * kPT;
+            if (i < kPiecesX)
+                *reinterpret_cast<bf16x8*>(&bx[(i >> 2) * kConvPix + 8 * conv_slot(i >> 2, i & 3)]) =
+                    vx[k];
+        }
+        if constexpr (NBP != 1) {
+            if (need_w) load_w();
+        }
+        if (need_w) {
 #pragma unroll
             for (int k = 0; k < kPerW; ++k) {
                 const int i = tid + k * kPT;
