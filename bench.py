@@ -191,6 +191,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": dict(roof, kernel="k_stepT<T=%d,rows=%d>" % (T, rows),
                          launch_ms=round(1e3 * t_k, 4),
+                         traffic_GBs=round(traf["bytes_per_launch"] / t_k / 1e9, 1) if traf else None,
                          algorithmic="%d FLOP/update x %d updates; %d B/cell x %d cells"
                                      % (FLOP_PER_UPDATE, cells * T, BYTES_PER_CELL_LAUNCH, cells)),
         "roofline_other": other,
@@ -260,6 +261,7 @@ def bench_batch(args):
             if e.status != rdc.RDC_E_NONFINITE:
                 raise
             diverged.append(i)
+    bu, bv = (t.clone() for t in b.current())       # the batch's final states (pooled)
     g.close()
     b.close()
     del zeros
@@ -284,6 +286,15 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t_single = e0.elapsed_time(e1) / 1e3
     wall_single = time.perf_counter() - t0
+    # every finite grid must end bit-identical to the same grid stepped alone
+    same = 0
+    for i, (sim, (nx, ny, pitch, off)) in enumerate(zip(ctxs, b.shapes)):
+        if i in diverged:
+            continue
+        su, sv = sim.current()
+        gu = bu[off:off + ny * pitch].view(ny, pitch)[:, :nx]
+        gv = bv[off:off + ny * pitch].view(ny, pitch)[:, :nx]
+        same += int(torch.equal(su, gu) and torch.equal(sv, gv))
     for sim in ctxs:
         sim.close()
     single = cells * steps / t_single / 1e9
@@ -298,6 +309,7 @@ def bench_batch(args):
         "per_grid_baseline": {"value": round(single, 2), "unit": "GCell-updates/s",
                               "seconds": round(t_single, 3), "wall_s": round(wall_single, 3)},
         "speedup_vs_per_grid": round(value / single, 2),
+        "finite_grids_bitwise_equal_to_per_grid": "%d/%d" % (same, len(sims) - len(diverged)),
         "diverged_grids": len(diverged),
         "diverged_eps_max": round(max(sims[i].params["eps"] for i in diverged), 5) if diverged else None,
         "tuning_us_per_step": tune,
