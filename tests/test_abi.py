@@ -126,3 +126,50 @@ def test_batch_create_rejects_bad_params(lib):
     s = lib.rdc_batch_create(1, d, ctypes.byref(_bufs()), 4096, None, ctypes.byref(out))
     assert s == rdc.RDC_E_INVAL
     assert "1/4" in lib.rdc_batch_last_error(None).decode()
+
+
+def test_timelapse_argument_checks(lib):
+    assert lib.rdc_set_timelapse(None, None, 0, 1) == rdc.RDC_E_INVAL
+
+
+def _nn_err(lib):
+    return lib.rdc_nn_last_error().decode()
+
+
+FAKE = 0x10000000      # 256-byte aligned, never dereferenced: the checks reject first
+
+
+@pytest.mark.parametrize("args,why", [
+    # x, ldx, w, bias, y, ldy, n, h, w, cin, cout, cout_store, relu
+    ((None, 32, FAKE, None, FAKE, 32, 1, 4, 64, 32, 32, 32, 1), "NULL"),
+    ((FAKE, 32, FAKE, None, FAKE, 32, 1, 4, 48, 32, 32, 32, 1), "multiple of 32"),
+    ((FAKE, 32, FAKE, None, FAKE, 32, 1, 4, 64, 24, 32, 32, 1), "cin % 16"),
+    ((FAKE, 32, FAKE, None, FAKE, 32, 1, 4, 64, 32, 48, 32, 1), "cout in"),
+    ((FAKE, 32, FAKE, None, FAKE, 32, 1, 4, 64, 32, 32, 33, 1), "cout_store"),
+    ((FAKE, 36, FAKE, None, FAKE, 32, 1, 4, 64, 32, 32, 32, 1), "strides"),
+    ((FAKE + 8, 32, FAKE, None, FAKE, 32, 1, 4, 64, 32, 32, 32, 1), "alignment")])
+def test_conv_argument_checks_run_before_any_launch(lib, args, why):
+    assert lib.rdc_nn_conv3x3(*args, None) == rdc.RDC_E_INVAL
+    assert why in _nn_err(lib)
+
+
+def test_nn_argument_checks(lib):
+    # weight gradient: channel counts must be multiples of 32
+    assert lib.rdc_nn_conv3x3_wgrad(FAKE, 32, FAKE, 32, FAKE, FAKE, None, 1, 4, 64, 16, 32,
+                                    None) == rdc.RDC_E_INVAL
+    assert "% 32" in _nn_err(lib)
+    # scratch size is zero for shapes the kernel rejects
+    assert lib.rdc_nn_wgrad_scratch_floats(1, 4, 16, 32, 32) == 0
+    assert lib.rdc_nn_wgrad_scratch_floats(1, 4, 64, 32, 32) > 0
+    assert lib.rdc_nn_loss_blocks(0) == 0 and lib.rdc_nn_loss_blocks(1000) >= 1
+    # apply needs phi and a positive f (the Euler bound divides by it)
+    assert lib.rdc_nn_apply(FAKE, FAKE, None, FAKE, 32, 64, 4096, FAKE, FAKE, 1, 4, 64, 1.0, 4.0,
+                            1.4, 0.3, None) == rdc.RDC_E_INVAL
+    assert lib.rdc_nn_apply(FAKE, FAKE, FAKE, FAKE, 32, 64, 4096, FAKE, FAKE, 1, 4, 64, 1.0, 4.0,
+                            0.0, 0.3, None) == rdc.RDC_E_INVAL
+    # front and state checks: sizes and ranges
+    assert lib.rdc_nn_front_check(FAKE, FAKE, 10, 64, 4, 0.5, FAKE, None) == rdc.RDC_E_INVAL
+    assert lib.rdc_nn_state_check(FAKE, FAKE, FAKE, 64, 64, 4, 1.0, -1.0, 1.4, 0.3, FAKE,
+                                  None) == rdc.RDC_E_INVAL
+    assert lib.rdc_nn_adam(None, FAKE, FAKE, FAKE, 10, 1e-3, 0.9, 0.999, 1e-8, 1.0,
+                           None) == rdc.RDC_E_INVAL
