@@ -346,6 +346,23 @@ def bench_uniform(args):
         e1.synchronize()
         t = e0.elapsed_time(e1) / 1e3
         res["T%d_r%d" % (T, rows)] = wl.nx * wl.ny * wl.steps / t / 1e9
+    sim.close()
+    # The FP64 variant (one step per launch, 40 B per cell-update) on the same inputs.
+    s64 = rdc.Sim(wl.nx, wl.ny, wl.params, "fp64")
+    s64.set_phi(wl.phi)
+    z64 = torch.zeros((wl.ny, wl.nx), dtype=torch.float64, device="cuda")
+    s64.write(z64, z64)
+    s64.stimulate(disks)
+    s64.step(4)
+    e0, e1 = _events()
+    n64 = 400
+    e0.record(s64.stream)
+    s64.step(n64)
+    e1.record(s64.stream)
+    e1.synchronize()
+    t64 = e0.elapsed_time(e1) / 1e3
+    fp64 = wl.nx * wl.ny * n64 / t64 / 1e9
+    s64.close()
     best = max(res, key=res.get)
     t1 = res["T1_r0"]
     out = {
@@ -357,9 +374,10 @@ def bench_uniform(args):
         "one_step_kernel_hbm": {"achieved_GBs": round(t1 * BYTES_PER_CELL_LAUNCH, 1),
                                 "peak_GBs": HBM_PEAK_GBS,
                                 "frac": round(t1 * BYTES_PER_CELL_LAUNCH / HBM_PEAK_GBS, 4)},
+        "fp64_one_step_kernel": {"gcells": round(fp64, 1), "achieved_GBs": round(fp64 * 40, 1),
+                                 "frac": round(fp64 * 40 / HBM_PEAK_GBS, 4), "steps": n64},
     }
     print(json.dumps(out), flush=True)
-    sim.close()
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0    # MI355X dense bf16

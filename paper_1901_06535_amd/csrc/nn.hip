@@ -70,14 +70,18 @@ __device__ __forceinline__ bf16x8 zero8() {
 // consumers keep separate memory counters, so the consumers never wait on
 // global memory and the next stage's loads overlap the current multiplies.
 // LDS rows are 64 bytes (32 channels); the four 16-byte slots of row r are
-// permuted by XOR with (r >> 1) & 3 so 32 lanes reading one slot of 32
-// consecutive rows spread over the banks.
+// permuted by XOR with (r >> 2) & 3, so any 16 consecutive rows read at one
+// slot cover all 64 banks (gfx950 serves a 16-byte-per-lane LDS access 16
+// lanes at a time; hardware counters read zero bank conflicts with it).
 constexpr int kConvRows = 8;                      // output rows per tile = consumer waves
 constexpr int kConvProducers = 4;                 // producer waves
 constexpr int kConvThreads = (kConvRows + kConvProducers) * 64;
 constexpr int kConvKc = 32;                       // input channels per stage
 constexpr int kConvPix = 32;                      // LDS elements per staged row
 
+#ifndef RDC_CONV_SWZ_SHIFT
+#define RDC_CONV_SWZ_SHIFT 2    // row bits that permute a row's four 16-byte LDS slots
+#endif
 #ifndef RDC_CONV_WG_PER_CU
 #define RDC_CONV_WG_PER_CU 1    // workgroups launched per CU (each sweeps a run of tiles)
 #endif
@@ -90,7 +94,7 @@ constexpr int conv_pixel_blocks() { return 2; }
 template <int NB>
 constexpr int conv_pass_blocks() { return NB % 2 == 0 ? 2 : 1; }
 
-__device__ __forceinline__ int conv_slot(int row, int slot) { return slot ^ ((row >> 1) & 3); }
+__device__ __forceinline__ int conv_slot(int row, int slot) { return slot ^ ((row >> RDC_CONV_SWZ_SHIFT) & 3); }
 
 template <int NBP, int PASSES, int P, bool RELU, bool BIAS>
 __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_tiles, int runs,
