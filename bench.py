@@ -386,7 +386,8 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0    # MI355X dense bf16
 def bench_surrogate(args):
     """Learned coarse stepper (K = 50 steps per network step): trained on the
     GPU on (t, t+50) pairs of 512^2 patches that the plain stepper generates
-    from random circuits (batch 4, Adam), then run on a 2048^2 circuit for
+    from random circuits (batch 4, Adam, half the iterations on the network's
+    own one-step predictions as inputs), then run on a 2048^2 circuit for
     50,000 steps with a plain-stepper check every 10 network steps and
     fallback when the front error exceeds one cell.  Reports its throughput
     and speedup against the plain stepper on the same grid and schedule, the
@@ -397,10 +398,10 @@ def bench_surrogate(args):
     if not os.path.exists(rdc.LIB_PATH):
         from paper_1901_06535_amd import build
         build.build()
-    K, batch, patch = 50, 4, 512
+    K, batch, patch, pushforward = 50, 4, 512, 0.5
     iters = max(1, args.train_pairs // batch)
     net = sg.UNet(seed=0)
-    tr = sg.Trainer(net, n=patch, batch=batch, K=K, seed=100)
+    tr = sg.Trainer(net, n=patch, batch=batch, K=K, seed=100, pushforward=pushforward)
     losses = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -498,6 +499,7 @@ def bench_surrogate(args):
                         "max_cells_more_than_1_cell_off": tracked["max_cells_off"],
                         "final_cells_more_than_1_cell_off": final_off},
         "training": {"seconds": round(t_train, 2), "iters": iters, "batch": batch,
+                     "pushforward": pushforward,
                      "pairs_per_s": round(iters * batch / t_train, 1),
                      "loss_first_100": float(np.mean(losses[:100])),
                      "loss_last_100": float(np.mean(losses[-100:])),

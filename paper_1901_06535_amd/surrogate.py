@@ -331,18 +331,31 @@ def training_batch_sims(n: int, count: int, seed: int, steps: int) -> List[input
 
 class Trainer:
     """Trains the network on pairs (state at t, state at t + K) that the
-    plain stepper generates on the fly from random circuits."""
+    plain stepper generates on the fly from random circuits.
+
+    With `pushforward` p > 0, a fraction p of the iterations (once a previous
+    pair of the same circuits exists) replaces the input S_t by the network's
+    own prediction of it from S_(t-K) (no gradient through that prediction),
+    keeping the plain S_(t+K) as the target: the network learns to correct
+    the kind of error it makes, which is what accumulates between the plain
+    stepper's checks."""
 
     def __init__(self, net: UNet, n: int = 256, batch: int = 8, K: int = 50, burn_in: int = 1000,
-                 seed: int = 100):
+                 seed: int = 100, pushforward: float = 0.0):
         import torch
         self.net, self.n, self.batch, self.K, self.burn_in = net, n, batch, K, burn_in
         self.seed = seed
+        self.pushforward = float(pushforward)
+        self.rng = np.random.default_rng(seed)
         self.ws = Workspace(net, batch, n, n, train=True)
         self.pitch = rdc.pitch_for(n)
         self.plane = self.pitch * n
         self.u_in = torch.empty(batch * self.plane, dtype=torch.float32, device=net.device)
         self.v_in = torch.empty_like(self.u_in)
+        # S_(t-K) of the current circuits and a spare pair, for pushforward
+        self.u_prev, self.v_prev, self.u_next, self.v_next = (
+            torch.empty_like(self.u_in) for _ in range(4))
+        self.prev_ok = False
         self.round = 0
         self._new_sims()
 
@@ -378,6 +391,7 @@ class Trainer:
         if self.now + self.K > self.burn_in + 40 * self.K:
             self.sims.close()
             self._new_sims()
+            self.prev_ok = False
         u, v = self.sims.current()
         s = self.net.stream.cuda_stream
         nb = 4 * self.batch * self.plane
@@ -388,7 +402,25 @@ class Trainer:
         return (_ptr(self.u_in), _ptr(self.v_in), _ptr(self.sims.planes[4]), _ptr(ut), _ptr(vt))
 
     def step(self, lr: float = 1e-3) -> float:
-        u, v, phi, ut, vt = self.pair()
+        u, v, phi, ut, vt = self.pair()          # (u, v) = plain S_t, (ut, vt) = S_(t+K)
+        if self.pushforward > 0:
+            s = self.net.stream.cuda_stream
+            nb = 4 * self.batch * self.plane
+            if self.prev_ok and self.rng.random() < self.pushforward:
+                # training input := the network's prediction of S_t from S_(t-K)
+                prep(self.net, self.ws, _ptr(self.u_prev), _ptr(self.v_prev), phi, self.pitch,
+                     self.plane)
+                forward(self.net, self.ws)
+                rdc.rdc_copy(_ptr(self.u_next), u, nb, s)          # keep the plain S_t
+                rdc.rdc_copy(_ptr(self.v_next), v, nb, s)
+                apply(self.net, self.ws, _ptr(self.u_prev), _ptr(self.v_prev), phi, u, v,
+                      self.pitch, self.plane, self.wls[0].params)
+                self.u_prev, self.u_next = self.u_next, self.u_prev
+                self.v_prev, self.v_next = self.v_next, self.v_prev
+            else:
+                rdc.rdc_copy(_ptr(self.u_prev), u, nb, s)
+                rdc.rdc_copy(_ptr(self.v_prev), v, nb, s)
+            self.prev_ok = True
         prep(self.net, self.ws, u, v, phi, self.pitch, self.plane)
         forward(self.net, self.ws)
         L = loss_and_grad(self.net, self.ws, u, v, ut, vt, self.pitch, self.plane)
@@ -401,8 +433,8 @@ class Trainer:
 
 
 def train(net: UNet, iters: int, n: int = 256, batch: int = 8, K: int = 50, lr: float = 1e-3,
-          seed: int = 100, log_every: int = 0) -> List[float]:
-    tr = Trainer(net, n=n, batch=batch, K=K, seed=seed)
+          seed: int = 100, log_every: int = 0, pushforward: float = 0.0) -> List[float]:
+    tr = Trainer(net, n=n, batch=batch, K=K, seed=seed, pushforward=pushforward)
     losses = []
     t0 = time.time()
     for it in range(iters):
