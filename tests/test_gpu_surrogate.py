@@ -131,3 +131,32 @@ def test_trained_network_runs_under_supervision(sg, trained):
     assert st["network_steps"] + st["plain_steps"] == 2000
     assert st["network_steps"] > 0
     assert st["tracked_windows"] == st["windows"]
+
+
+def test_pushforward_training_uses_the_networks_own_predictions(sg):
+    """With pushforward, the input of some iterations is the network's
+    prediction of S_t from S_(t-K): it differs from the plain S_t, stays
+    close to it once trained, and training still lowers the loss."""
+    import torch
+    net = sg.UNet(seed=1)
+    tr = sg.Trainer(net, n=256, batch=4, K=K, seed=300, pushforward=1.0)
+    losses = [tr.step(1e-3) for _ in range(150)]
+    assert tr.prev_ok
+    # one more iteration by hand: the input the trainer used vs the plain state
+    u_plain = None
+    orig_pair = tr.pair
+
+    def spy():
+        nonlocal u_plain
+        out = orig_pair()
+        u_plain = tr.u_in.clone()
+        return out
+    tr.pair = spy
+    tr.step(1e-3)
+    used = tr.u_in
+    diff = (used - u_plain).abs()
+    tr.close()
+    print("  loss first 10 %.3g last 10 %.3g; |pushforward input - plain| max %.3g mean %.3g"
+          % (np.mean(losses[:10]), np.mean(losses[-10:]), diff.max().item(), diff.mean().item()))
+    assert np.isfinite(losses).all() and np.mean(losses[-10:]) < 0.5 * np.mean(losses[:10])
+    assert diff.max().item() > 0 and diff.mean().item() < 0.05
