@@ -347,22 +347,28 @@ def bench_uniform(args):
         t = e0.elapsed_time(e1) / 1e3
         res["T%d_r%d" % (T, rows)] = wl.nx * wl.ny * wl.steps / t / 1e9
     sim.close()
-    # The FP64 variant (one step per launch, 40 B per cell-update) on the same inputs.
+    # The FP64 variants on the same inputs: one step per launch (40 B per
+    # cell-update, HBM-bound) and T steps per launch on 128-column tiles.
     s64 = rdc.Sim(wl.nx, wl.ny, wl.params, "fp64")
     s64.set_phi(wl.phi)
     z64 = torch.zeros((wl.ny, wl.nx), dtype=torch.float64, device="cuda")
-    s64.write(z64, z64)
-    s64.stimulate(disks)
-    s64.step(4)
-    e0, e1 = _events()
-    n64 = 400
-    e0.record(s64.stream)
-    s64.step(n64)
-    e1.record(s64.stream)
-    e1.synchronize()
-    t64 = e0.elapsed_time(e1) / 1e3
-    fp64 = wl.nx * wl.ny * n64 / t64 / 1e9
+    n64 = 480
+    res64 = {}
+    for T, rows in ((1, 0), (4, 56), (6, 56), (8, 48), (8, 56), (8, 64)):
+        s64.set_block(T)
+        s64.set_tile_rows(rows)
+        s64.write(z64, z64)
+        s64.stimulate(disks)
+        s64.step(8)
+        e0, e1 = _events()
+        e0.record(s64.stream)
+        s64.step(n64)
+        e1.record(s64.stream)
+        e1.synchronize()
+        res64["T%d_r%d" % (T, rows)] = wl.nx * wl.ny * n64 / (e0.elapsed_time(e1) / 1e3) / 1e9
     s64.close()
+    fp64 = res64["T1_r0"]
+    best64 = max(res64, key=res64.get)
     best = max(res, key=res.get)
     t1 = res["T1_r0"]
     out = {
@@ -376,6 +382,8 @@ def bench_uniform(args):
                                 "frac": round(t1 * BYTES_PER_CELL_LAUNCH / HBM_PEAK_GBS, 4)},
         "fp64_one_step_kernel": {"gcells": round(fp64, 1), "achieved_GBs": round(fp64 * 40, 1),
                                  "frac": round(fp64 * 40 / HBM_PEAK_GBS, 4), "steps": n64},
+        "fp64_per_variant_gcells": {k: round(v, 1) for k, v in res64.items()},
+        "fp64_best": best64,
     }
     print(json.dumps(out), flush=True)
 

@@ -88,15 +88,16 @@ def _search(step, set_shape, stream, Ts: Iterable[int], rows: Iterable[int],
 
 def tune_sim(sim, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = DEFAULT_ROWS,
              launches: int = 24, use_cache: bool = True) -> Dict:
-    """Pick (T, rows) for an FP32 `rdc.Sim`, set them on it and return
-    {"T", "rows", "us_per_step", "table", "cached"}."""
+    """Pick (T, rows) for an `rdc.Sim` (FP32 or FP64), set them on it and
+    return {"T", "rows", "us_per_step", "table", "cached"}."""
     from . import rdc
-    key = key_for("single", "%dx%d" % (sim.nx, sim.ny))
+    key = key_for("single" if sim.dtype == "fp32" else "single_" + sim.dtype,
+                  "%dx%d" % (sim.nx, sim.ny))
     hit = _load().get(key) if use_cache else None
     if hit:
         rec = dict(hit, cached=True)
     else:
-        scratch = rdc.Sim(sim.nx, sim.ny, sim.params, "fp32", device=sim.device,
+        scratch = rdc.Sim(sim.nx, sim.ny, sim.params, sim.dtype, device=sim.device,
                           stream=sim.stream)
 
         def set_shape(T, r):

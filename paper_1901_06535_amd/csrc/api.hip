@@ -299,18 +299,18 @@ rdc_status rdc_step(rdc_ctx* c, int64_t n) {
     if (c->step + n > INT32_MAX - 8)
         return fail(c, RDC_E_STATE, "step counter would overflow the int32 arrival range");
     DeviceGuard g(c->device);
-    const int T = c->dtype == RDC_FP64 ? 1 : (c->T > 0 ? c->T : auto_block(c));
+    const int T = c->T > 0 ? c->T : auto_block(c);
     const int rows = c->tile_rows > 0 ? c->tile_rows : rdc::tile_rows_default();
+    const bool f64 = c->dtype == RDC_FP64;
     while (n > 0) {
         const int k = n < T ? static_cast<int>(n) : T;
         hipError_t e;
-        if (c->dtype == RDC_FP64) {
-            e = rdc::launch_step1(step_args<double>(c), c->stream);
-        } else if (k == 1) {
-            e = rdc::launch_step1(step_args<float>(c), c->stream);
-        } else {
-            e = rdc::launch_stepT(step_args<float>(c), k, rows, c->stream);
-        }
+        if (k == 1)
+            e = f64 ? rdc::launch_step1(step_args<double>(c), c->stream)
+                    : rdc::launch_step1(step_args<float>(c), c->stream);
+        else
+            e = f64 ? rdc::launch_stepT(step_args<double>(c), k, rows, c->stream)
+                    : rdc::launch_stepT(step_args<float>(c), k, rows, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->cur ^= 1;
         c->step += k;

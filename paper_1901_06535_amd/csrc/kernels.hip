@@ -146,6 +146,16 @@ void k_stepT(StepArgs<float> a, int tiles_x, int ntiles, int per_xcd) {
     step_tile<T, R, OUT>(a, tile % tiles_x, tile / tiles_x, lds);
 }
 
+template <int T, int R, bool OUT>
+__global__ __launch_bounds__(kTileWaves * 64, (tile_waves_per_simd<R, OUT>()))
+void k_stepT64(StepArgs<double> a, int tiles_x, int ntiles, int per_xcd) {
+    __shared__ double2 lds[kTileWaves * R][64];
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * per_xcd + (b >> 3);   // XCD-contiguous runs, as k_stepT
+    if (tile >= ntiles) return;
+    step_tile64<T, R, OUT>(a, tile % tiles_x, tile / tiles_x, lds);
+}
+
 // ---------------------------------------------------------------- stimulation etc.
 
 template <typename Real>
@@ -263,6 +273,36 @@ hipError_t stepT_rows(const StepArgs<float>& a, int T, hipStream_t s) {
     }
 }
 
+template <int T, int R>
+hipError_t stepT64_impl(const StepArgs<double>& a, hipStream_t s) {
+    using G = TileGeom64<T, R>;
+    const int tiles_x = (a.nx + G::BX - 1) / G::BX;
+    const int tiles_y = (a.ny + G::BY - 1) / G::BY;
+    const int ntiles = tiles_x * tiles_y;
+    const int per_xcd = (ntiles + 7) / 8;
+    const dim3 grid(8 * per_xcd), block(kTileWaves * 64);
+    if (a.arrival || a.tl)
+        hipLaunchKernelGGL((k_stepT64<T, R, true>), grid, block, 0, s, a, tiles_x, ntiles, per_xcd);
+    else
+        hipLaunchKernelGGL((k_stepT64<T, R, false>), grid, block, 0, s, a, tiles_x, ntiles,
+                           per_xcd);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t stepT64_rows(const StepArgs<double>& a, int T, hipStream_t s) {
+    switch (T) {
+        case 2: return stepT64_impl<2, R>(a, s);
+        case 3: return stepT64_impl<3, R>(a, s);
+        case 4: return stepT64_impl<4, R>(a, s);
+        case 5: return stepT64_impl<5, R>(a, s);
+        case 6: return stepT64_impl<6, R>(a, s);
+        case 7: return stepT64_impl<7, R>(a, s);
+        case 8: return stepT64_impl<8, R>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename Real>
 hipError_t stimulate_impl(Real* u, int64_t pitch, int nx, int ny, const Disks& d,
                           int32_t* arrival, int64_t apitch, int step, hipStream_t s) {
@@ -308,6 +348,16 @@ hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s
         case 56: return stepT_rows<7>(a, T, s);
         case 64: return stepT_rows<8>(a, T, s);
         case 80: return stepT_rows<10>(a, T, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stepT(const StepArgs<double>& a, int T, int rows, hipStream_t s) {
+    switch (rows) {
+        case 48: return stepT64_rows<6>(a, T, s);
+        case 56: return stepT64_rows<7>(a, T, s);
+        case 64: return stepT64_rows<8>(a, T, s);
+        case 80: return stepT64_rows<10>(a, T, s);
         default: return hipErrorInvalidValue;
     }
 }

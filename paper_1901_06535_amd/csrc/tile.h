@@ -319,5 +319,179 @@ __device__ __forceinline__ void step_tile(const StepArgs<float>& a, int tx, int 
 }
 
 
+// ---------------------------------------------------------------- FP64 T-step tile
+
+// The FP64 variant of step_tile: each lane owns 2 adjacent cells (16 bytes)
+// of a row, so a wave covers 128 columns and an LDS row is 1 KB as in FP32;
+// the column halo is T rounded up to whole lanes.  Same per-cell update as
+// the one-step FP64 kernel, so every launch shape is bit-identical to it.
+constexpr int kTileCols64 = 128;
+
+template <int T, int R>
+struct TileGeom64 {
+    static constexpr int HX = (T + 1) & ~1;
+    static constexpr int BX = kTileCols64 - 2 * HX;
+    static constexpr int BY = kTileWaves * R - 2 * T;
+};
+
+__device__ __forceinline__ double2 buf_load2d(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+    return make_double2(__hiloint2double(v[1], v[0]), __hiloint2double(v[3], v[2]));
+}
+__device__ __forceinline__ double buf_load1d(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+    return __hiloint2double(v[1], v[0]);
+}
+__device__ __forceinline__ void buf_store2d(__amdgpu_buffer_rsrc_t r, int byte_off, double a0,
+                                            double a1) {
+    __attribute__((ext_vector_type(4))) unsigned int v;
+    v[0] = __double2loint(a0);
+    v[1] = __double2hiint(a0);
+    v[2] = __double2loint(a1);
+    v[3] = __double2hiint(a1);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, byte_off, 0, kStoreAux);
+}
+__device__ __forceinline__ void buf_store1d(__amdgpu_buffer_rsrc_t r, int byte_off, double a) {
+    __attribute__((ext_vector_type(2))) unsigned int v;
+    v[0] = __double2loint(a);
+    v[1] = __double2hiint(a);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, byte_off, 0, kStoreAux);
+}
+
+template <int T, int R, bool OUT>
+__device__ __forceinline__ void step_tile64(const StepArgs<double>& a, int tx, int ty,
+                                            double2 (&lds)[kTileWaves * R][64]) {
+    using G = TileGeom64<T, R>;
+    constexpr int HX = G::HX, BX = G::BX;
+    constexpr int EY = kTileWaves * R;
+    static_assert(G::BY > 0 && BX > 0, "tile too small for T");
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nx = a.nx, ny = a.ny;
+    const int64_t P = a.pitch;
+    const int gx = tx * BX - HX + 2 * lane;   // first global column of this lane
+    const int gy0 = ty * G::BY - T;           // global row of tile row 0
+    const bool fast_x = gx >= 0 && gx + 1 < nx;
+    int xb[2];                                // byte offsets of this lane's 2 columns
+#pragma unroll
+    for (int c = 0; c < 2; ++c) xb[c] = 8 * reflect_index(gx + c, nx);
+    const int row_bytes = static_cast<int>(P * 8);
+
+    double vr[R][2], pr[R][2], un[R][2];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int r = w + kTileWaves * k;
+        const int64_t off = (int64_t)reflect_index(gy0 + r, ny) * P;
+        const auto ru = row_rsrc(a.u + off, row_bytes);
+        const auto rv = row_rsrc(a.v + off, row_bytes);
+        const auto rp = row_rsrc(a.phi + off, row_bytes);
+        double2 uu, vv, pp;
+        if (fast_x) {
+            uu = buf_load2d(ru, xb[0]);
+            vv = buf_load2d(rv, xb[0]);
+            pp = buf_load2d(rp, xb[0]);
+        } else {
+            uu = make_double2(buf_load1d(ru, xb[0]), buf_load1d(ru, xb[1]));
+            vv = make_double2(buf_load1d(rv, xb[0]), buf_load1d(rv, xb[1]));
+            pp = make_double2(buf_load1d(rp, xb[0]), buf_load1d(rp, xb[1]));
+        }
+        lds[r][lane] = uu;
+        vr[k][0] = vv.x;
+        vr[k][1] = vv.y;
+        pr[k][0] = scaled_phi(pp.x, a.k);
+        pr[k][1] = scaled_phi(pp.y, a.k);
+    }
+
+    const bool out_lane = lane >= HX / 2 && lane < 64 - HX / 2;
+    int ar[OUT ? R : 1][2];
+    double tm[OUT ? R : 1][2];
+    if (OUT) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = w + kTileWaves * k;
+            const int gy = gy0 + r;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bool in = out_lane && r >= T && r < EY - T && gy < ny && gx + c < nx;
+                ar[k][c] = in && a.arrival ? a.arrival[(int64_t)gy * a.apitch + gx + c] : 0;
+                tm[k][c] = in && a.tl ? a.tl[(int64_t)gy * a.tpitch + gx + c] : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int t = 1; t <= T; ++t) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = w + kTileWaves * k;
+            if (r >= t && r < EY - t) {
+                const double2 c = lds[r][lane];
+                const double2 n = lds[r - 1][lane];
+                const double2 s = lds[r + 1][lane];
+                const double west = from_west_lane(c.y);
+                const double east = from_east_lane(c.x);
+                cell_update(c.x, west, c.y, n.x, s.x, vr[k][0], pr[k][0], a.k, un[k][0], vr[k][0]);
+                cell_update(c.y, c.x, east, n.y, s.y, vr[k][1], pr[k][1], a.k, un[k][1], vr[k][1]);
+                if (OUT && r >= T && r < EY - T) {
+                    if (a.arrival) {
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+                            if (ar[k][e] == kNever && un[k][e] >= a.theta) ar[k][e] = a.step0 + t;
+                    }
+                    if (a.tl && (a.step0 + t) % a.tl_rate == 0) {
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+                            if (un[k][e] > tm[k][e]) tm[k][e] = un[k][e];
+                    }
+                }
+            }
+        }
+        if (t < T) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int r = w + kTileWaves * k;
+                if (r >= t && r < EY - t) lds[r][lane] = make_double2(un[k][0], un[k][1]);
+            }
+            __syncthreads();
+        }
+    }
+
+    bool bad = false;
+    if (out_lane) {
+        const int xo = 8 * gx;   // gx >= 0 for output lanes
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int r = w + kTileWaves * k;
+            const int gy = gy0 + r;
+            if (r < T || r >= EY - T || gy >= ny) continue;
+            const int64_t off = (int64_t)gy * P;
+            const auto ru = row_rsrc(a.u_out + off, row_bytes);
+            const auto rv = row_rsrc(a.v_out + off, row_bytes);
+            if (gx + 1 < nx) {
+                buf_store2d(ru, xo, un[k][0], un[k][1]);
+                buf_store2d(rv, xo, vr[k][0], vr[k][1]);
+                bad |= !finite2(un[k][0], vr[k][0]) || !finite2(un[k][1], vr[k][1]);
+            } else if (gx < nx) {
+                buf_store1d(ru, xo, un[k][0]);
+                buf_store1d(rv, xo, vr[k][0]);
+                bad |= !finite2(un[k][0], vr[k][0]);
+            }
+            if (OUT && a.arrival) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (gx + c < nx) a.arrival[(int64_t)gy * a.apitch + gx + c] = ar[k][c];
+            }
+            if (OUT && a.tl) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    if (gx + c < nx) a.tl[(int64_t)gy * a.tpitch + gx + c] = tm[k][c];
+            }
+        }
+    }
+    if (bad) *a.flag = 1;
+}
+
 }  // namespace dev
 }  // namespace rdc

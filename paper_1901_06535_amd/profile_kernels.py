@@ -3,7 +3,8 @@
 Runs, on the circuit workload's 4096x4096 grid: a few launches of the
 temporal-blocking kernel for every (steps per launch, tile rows) pair the
 benchmark's autotuner may pick; on a 16384x16384 grid: a few launches of the
-one-step kernel; and three 1 GiB launches of the plain copy kernel (the
+FP32 and FP64 one-step kernels and of the FP64 T-step kernel (T=8, 56 and 64
+rows); and three 1 GiB launches of the plain copy kernel (the
 reference reading that scales memory counters to bytes).  Under
 
     rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_1901_06535_amd.profile_kernels
@@ -52,6 +53,10 @@ def source_hash() -> str:
 def _short(name: str) -> str:
     n = name.replace("void ", "").replace("rdc::nn::(anonymous namespace)::", "")
     n = n.replace("rdc::(anonymous namespace)::", "")
+    m = re.match(r"k_stepT64<(\d+), (\d+), (\w+)>", n)
+    if m:
+        return "k_stepT64<T=%s,rows=%d%s>" % (m.group(1), 8 * int(m.group(2)),
+                                             ",arrival" if m.group(3) == "true" else "")
     m = re.match(r"k_stepT<(\d+), (\d+), (\w+)>", n)
     if m:
         return "k_stepT<T=%s,rows=%d%s>" % (m.group(1), 8 * int(m.group(2)),
@@ -95,8 +100,11 @@ def summarize(fetch_csv: str, write_csv: str, out_json: str) -> None:
             continue
         rd, wr = f[k][0] * 1024 * sf, w[k][0] * 1024 * sw
         m = re.match(r"k_stepT<T=(\d+),rows=(\d+)>$", k)
+        m64 = re.match(r"k_stepT64<T=(\d+),rows=(\d+)>$", k)
         key = ("stepT_T%s_r%s_4096x4096" % m.groups()) if m else (
-            "step1_16384x16384" if k == "k_step1<float>" else None)
+            ("stepT64_T%s_r%s_16384x16384" % m64.groups()) if m64 else
+            {"k_step1<float>": "step1_16384x16384",
+             "k_step1<double>": "step1_f64_16384x16384"}.get(k))
         print("%-28s n=%2d fetch_KiB=%12.1f write_KiB=%12.1f -> read_MB=%9.1f written_MB=%9.1f"
               % (k, f[k][1], f[k][0], w[k][0], rd / 1e6, wr / 1e6))
         if key:
@@ -106,6 +114,7 @@ def summarize(fetch_csv: str, write_csv: str, out_json: str) -> None:
         json.dump(rec, fh, indent=1)
 
 CANDIDATES = [(T, r) for T in (4, 6, 8) for r in (48, 56, 64, 80)]
+CANDIDATES64 = [(8, 56), (8, 64)]
 LAUNCHES = 4
 
 
@@ -148,6 +157,21 @@ def main():
     big.synchronize()
     log.append({"kernel": "k_step1<float>", "grid": [n, n], "launches": LAUNCHES})
     big.close()
+
+    # FP64 on the same grid: the one-step kernel and the T-step kernel.
+    b64 = rdc.Sim(n, n, inputs.PARAMS_WORKLOAD, "fp64")
+    b64.set_phi((0.04 + 0.04 * rng.random((n, n))).astype(np.float64))
+    b64.set_block(1)
+    b64.step(LAUNCHES)
+    log.append({"kernel": "k_step1<double>", "grid": [n, n], "launches": LAUNCHES})
+    for T, rows in CANDIDATES64:
+        b64.set_block(T)
+        b64.set_tile_rows(rows)
+        b64.step(LAUNCHES * T)
+        log.append({"kernel": "k_stepT64<T=%d,rows=%d>" % (T, rows), "grid": [n, n],
+                    "launches": LAUNCHES})
+    b64.synchronize()
+    b64.close()
 
     nb = 1 << 30
     src = torch.zeros(nb // 4, dtype=torch.float32, device="cuda")

@@ -173,10 +173,20 @@ static void fp64_context(void) {
     b.phi = dev(plane * 8); b.pitch = pitch;
     rdc_ctx *c = NULL;
     EXPECT(rdc_create(nx, ny, RDC_FP64, &b, NULL, &c) == RDC_OK);
-    EXPECT(rdc_set_block(c, 8) == RDC_OK);         /* FP64 always steps one at a time */
+    EXPECT(rdc_set_block(c, 1) == RDC_OK);
     long before = shim_launches();
     EXPECT(rdc_step(c, 5) == RDC_OK);
     EXPECT(shim_launches() - before == 5);
+    const int rows[] = {48, 56, 64, 80};
+    for (int T = 2; T <= 8; ++T) {
+        for (int r = 0; r < 4; ++r) {
+            EXPECT(rdc_set_block(c, T) == RDC_OK);
+            EXPECT(rdc_set_tile_rows(c, rows[r]) == RDC_OK);
+            before = shim_launches();
+            EXPECT(rdc_step(c, 19) == RDC_OK);
+            EXPECT(shim_launches() - before == (19 + T - 1) / T);
+        }
+    }
     int32_t x = 0, y = 0, r = 5;
     EXPECT(rdc_stimulate(c, &x, &y, &r, 1) == RDC_OK);
     double *h = calloc((size_t)nx * ny, sizeof(double));

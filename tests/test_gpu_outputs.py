@@ -15,11 +15,12 @@ def _state(nx, ny, seed):
     return u, v, phi
 
 
-@pytest.mark.parametrize("rate", [1, 3, 7])
-def test_fp64_timelapse_bitwise_equals_oracle(rate):
+@pytest.mark.parametrize("rate,T", [(1, 1), (3, 1), (7, 1), (1, 8), (3, 5), (7, 8)])
+def test_fp64_timelapse_bitwise_equals_oracle(rate, T):
     nx, ny = 96, 80
     u, v, phi = _state(nx, ny, 31)
     s = rdc.Sim(nx, ny, inputs.PARAMS_WORKLOAD, "fp64")
+    s.set_block(T)
     s.set_phi(phi)
     s.write(u, v)
     s.stimulate([(40, 30, 5)])

@@ -138,20 +138,48 @@ SHAPES = [(1, 1), (1, 7), (7, 1), (2, 2), (8, 8), (3, 300), (300, 3), (65, 63), 
 
 @pytest.mark.parametrize("ny,nx", SHAPES)
 def test_small_and_ragged_grids_fp64_bitwise(ny, nx):
-    print_case("fp64 %dx%d" % (ny, nx))
     u, v, phi = inputs.random_state(nx, ny, seed=nx * 1000 + ny, umax=0.02, vmax=0.02)
     disks = [(nx // 2, ny // 2, 2), (0, 0, 1)]
     run = oracle.Run(u, v, phi, inputs.PARAMS_WORKLOAD)
     run.stimulate(disks)
     run.advance(60)
-    s = rdc.Sim(nx, ny, inputs.PARAMS_WORKLOAD, "fp64")
-    s.set_phi(phi)
-    s.write(u, v)
-    s.stimulate(disks)
-    s.step(60)
-    gu, gv = s.read()
-    s.close()
-    assert np.array_equal(gu, run.u) and np.array_equal(gv, run.v)
+    for T, rows in ((1, 0), (3, 48), (8, 48), (8, 80)):
+        print_case("fp64 %dx%d T=%d rows=%d" % (ny, nx, T, rows))
+        s = rdc.Sim(nx, ny, inputs.PARAMS_WORKLOAD, "fp64")
+        s.set_phi(phi)
+        s.write(u, v)
+        s.set_block(T)
+        s.set_tile_rows(rows)
+        s.stimulate(disks)
+        s.step(60)
+        gu, gv = s.read()
+        s.close()
+        assert np.array_equal(gu, run.u) and np.array_equal(gv, run.v), (T, rows)
+
+
+def test_every_fp64_launch_shape_is_bitwise_equal_to_the_oracle():
+    u, v, phi, disks = _ragged_case()
+    ny, nx = u.shape
+    run = oracle.Run(u, v, phi, inputs.PARAMS_WORKLOAD)
+    run.stimulate(disks)
+    run.advance(23)
+    run.stimulate(disks[:3])
+    run.advance(14)
+    for rows in (48, 56, 64, 80):
+        for T in range(2, 9):
+            print_case("fp64 T=%d rows=%d" % (T, rows))
+            s = rdc.Sim(nx, ny, inputs.PARAMS_WORKLOAD, "fp64")
+            s.set_phi(phi)
+            s.write(u, v)
+            s.set_block(T)
+            s.set_tile_rows(rows)
+            s.stimulate(disks)
+            s.step(23)
+            s.stimulate(disks[:3])
+            s.step(14)
+            gu, gv = s.read()
+            s.close()
+            assert np.array_equal(gu, run.u) and np.array_equal(gv, run.v), (T, rows)
 
 
 @pytest.mark.parametrize("ny,nx", SHAPES)
@@ -294,11 +322,12 @@ def circuit_case():
     return wl, run
 
 
-def test_circuit_fp64_bitwise(circuit_case):
+@pytest.mark.parametrize("T,rows", [(1, 0), (8, 56)])
+def test_circuit_fp64_bitwise(circuit_case, T, rows):
     wl, run = circuit_case
-    print_case("circuit 512^2 fp64")
+    print_case("circuit 512^2 fp64 T=%d rows=%d" % (T, rows))
     assert np.isfinite(run.u).all()
-    s = make_sim(wl, "fp64", arrival=True)
+    s = make_sim(wl, "fp64", T=T, rows=rows, arrival=True)
     s.run_schedule(wl.stimuli, wl.steps)
     u, v = s.read()
     assert np.array_equal(u, run.u) and np.array_equal(v, run.v)
