@@ -83,7 +83,9 @@ typedef struct {
  * >= nx) and binds the current HIP device and `hip_stream`.  Parameters start
  * at Table 1 with phi from the caller's plane; the state is whatever the u[0]
  * and v[0] planes hold; the step counter is 0.
- * Errors: RDC_E_INVAL for nx or ny < 1, a bad buffer or a NULL `out`;
+ * Errors: RDC_E_INVAL for nx or ny < 1, ny > 1048560 (the one-step kernel's
+ * launch grid), a row of 2 GiB or more (pitch times the element size), a bad
+ * buffer or a NULL `out`;
  * RDC_E_NOMEM / RDC_E_DEVICE if the small device status word cannot be made. */
 rdc_status rdc_create(int32_t nx, int32_t ny, rdc_dtype dtype, const rdc_buffers *bufs,
                       void *hip_stream, rdc_ctx **out);

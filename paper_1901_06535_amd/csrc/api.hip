@@ -181,6 +181,10 @@ rdc_status rdc_create(int32_t nx, int32_t ny, rdc_dtype dtype, const rdc_buffers
     if (!b) return fail(nullptr, RDC_E_INVAL, "buffers is NULL");
     if (b->pitch < nx || b->pitch % 64 != 0)
         return fail(nullptr, RDC_E_INVAL, "pitch must be >= nx and a multiple of 64");
+    if (b->pitch > INT32_MAX / (dtype == RDC_FP64 ? 8 : 4))
+        return fail(nullptr, RDC_E_INVAL, "row too long: pitch times element size must be < 2 GiB");
+    if (ny > rdc::max_rows())
+        return fail(nullptr, RDC_E_INVAL, "ny above the launch grid's row limit");
     const void* planes[5] = {b->u[0], b->u[1], b->v[0], b->v[1], b->phi};
     for (const void* p : planes) {
         if (!p) return fail(nullptr, RDC_E_INVAL, "a buffer is NULL");

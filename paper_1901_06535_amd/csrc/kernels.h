@@ -41,6 +41,9 @@ hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s
 // The same for FP64 (tiles of 128 columns, 2 cells per lane).
 hipError_t launch_stepT(const StepArgs<double>& a, int T, int rows, hipStream_t s);
 bool tile_rows_supported(int rows);
+// Most rows a grid may have: the one-step kernel's launch grid covers
+// kStep1Rows rows per block row, at most 65535 block rows.
+int max_rows();
 int tile_rows_default();
 
 // Catalytic stimulation: u := 1 on up to kMaxDisks disks per launch.

@@ -341,6 +341,7 @@ bool tile_rows_supported(int rows) {
     return rows == 48 || rows == 56 || rows == 64 || rows == 80;
 }
 int tile_rows_default() { return 56; }
+int max_rows() { return 65535 * kStep1Rows; }
 
 hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s) {
     switch (rows) {

@@ -51,12 +51,13 @@ def _bufs(pitch=64, base=0x10000000):
     return b
 
 
-@pytest.mark.parametrize("nx,ny,pitch,why", [
-    (0, 4, 64, "nx and ny"), (4, 0, 64, "nx and ny"), (65, 4, 64, "pitch"),
-    (4, 4, 96, "pitch")])
-def test_create_rejects_bad_shape_before_touching_the_device(lib, nx, ny, pitch, why):
+@pytest.mark.parametrize("nx,ny,pitch,dtype,why", [
+    (0, 4, 64, 0, "nx and ny"), (4, 0, 64, 0, "nx and ny"), (65, 4, 64, 0, "pitch"),
+    (4, 4, 96, 0, "pitch"), (4, 4, 1 << 29, 0, "row too long"),
+    (4, 4, 1 << 28, 1, "row too long"), (4, 1048561, 64, 0, "row limit")])
+def test_create_rejects_bad_shape_before_touching_the_device(lib, nx, ny, pitch, dtype, why):
     out = ctypes.c_void_p()
-    s = lib.rdc_create(nx, ny, rdc.RDC_FP32, ctypes.byref(_bufs(pitch)), None, ctypes.byref(out))
+    s = lib.rdc_create(nx, ny, dtype, ctypes.byref(_bufs(pitch)), None, ctypes.byref(out))
     assert s == rdc.RDC_E_INVAL and out.value is None
     assert why in rdc.rdc_last_error(None)
 
