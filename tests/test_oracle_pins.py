@@ -458,3 +458,36 @@ def test_unstable_tracker_matches_brute_force():
         u, v = oracle.step(u, v, phi, wl.params)
     assert np.array_equal(run.unstable.astype(bool), mask)
     assert run.first_unstable == first
+
+
+def _front_speed(params, phi, nx=700, ny=3, steps=30000, x1=150, x2=550):
+    """Cells per step of a planar wave in a strip of excitable medium (phi
+    uniform), started from the settled rest state by a disk at the west end;
+    from the arrival times (first step with u >= 0.5) at two columns."""
+    z = np.zeros((ny, nx))
+    ph = np.full((ny, nx), phi)
+    rest = oracle.Run(z, z, ph, params)
+    rest.advance(3000)
+    run = oracle.Run(rest.u, rest.v, ph, params, track_arrival=True)
+    run.stimulate([(0, ny // 2, 4)])
+    run.advance(steps)
+    a = run.arrival
+    assert (a[:, x2] < oracle.NEVER).all()
+    # planar: every row of the strip arrives at the same step
+    assert (a[:, x1] == a[0, x1]).all() and (a[:, x2] == a[0, x2]).all()
+    return (x2 - x1) / float(a[0, x2] - a[0, x1])
+
+
+def test_front_speed_sanity():
+    """Sanity (not a paper value): a planar front moves at a steady 0.021-0.022
+    cells per step at the workload parameters, about 46 steps per cell, the
+    figure the circuit generator's space-time spacing rule bounds from above
+    (0.03); at Table 1 (smaller D_u, larger eps) it is slower."""
+    c = _front_speed(P, inputs.PHI_ACTIVE_TABLE1)
+    c_half = _front_speed(P, inputs.PHI_ACTIVE_TABLE1, x1=150, x2=350)
+    print("  front speed %.5f cells/step (first half %.5f)" % (c, c_half))
+    assert 0.020 <= c <= 0.023
+    assert abs(c_half - c) <= 0.02 * c              # steady, not accelerating
+    c1 = _front_speed(inputs.PARAMS_TABLE1, inputs.PHI_ACTIVE_TABLE1, steps=45000)
+    print("  Table 1: %.5f cells/step" % c1)
+    assert 0.010 <= c1 < 0.8 * c
