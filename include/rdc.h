@@ -296,6 +296,33 @@ rdc_status rdc_nn_conv3x3(const void *x, int32_t ldx, const void *w, const float
                           int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
                           int32_t cout, int32_t cout_store, int32_t relu, void *stream);
 
+/* rdc_nn_conv3x3 (bias added, ReLU applied) on a concatenation whose first
+ * up_c channels are the nearest 2x upsampling of a half-resolution tensor
+ * `xu` (n x h/2 x wd/2 pixels, stride ldu) and whose channels [up_c, cin)
+ * are channels [up_c, cin) of x (stride ldx): the decoder step of a U-Net,
+ * with the upsampled part read straight from the coarse level instead of
+ * being written out first.  Bit-identical to rdc_nn_up2 into channels
+ * [0, up_c) of x followed by rdc_nn_conv3x3.  Requires h even, wd % 64 == 0,
+ * up_c a multiple of 32 in 32..cin, cout in {32, 64, 128}, ldu % 8 == 0, xu
+ * 16-byte aligned; channels [0, up_c) of x are not read. */
+rdc_status rdc_nn_conv3x3_up(const void *x, int32_t ldx, const void *xu, int32_t ldu,
+                             int32_t up_c, const void *w, const float *bias, void *y,
+                             int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
+                             int32_t cout, int32_t cout_store, void *stream);
+
+/* rdc_nn_conv3x3 (bias added, ReLU applied) whose input is built while it is
+ * loaded from the stepper planes u, v, phi (fp32, row pitch `pitch`, image i
+ * at i*plane_stride): channels bf16(su u), bf16(sv v), bf16(sp phi), zeros
+ * up to cin -- the network's first layer without the input tensor.
+ * Bit-identical to rdc_nn_prep followed by rdc_nn_conv3x3.  Requires
+ * cin in {16, 32}, cout in {32, 64, 128}, pitch >= wd, plane_stride >=
+ * pitch*h. */
+rdc_status rdc_nn_conv3x3_planes(const float *u, const float *v, const float *phi,
+                                 int64_t pitch, int64_t plane_stride, float su, float sv,
+                                 float sp, const void *w, const float *bias, void *y,
+                                 int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
+                                 int32_t cout, int32_t cout_store, void *stream);
+
 /* Weights of the input-gradient convolution: wd[tap][ci][co] =
  * bf16(w[8 - tap][co][ci]); rdc_nn_conv3x3 with them (cin <-> cout, no bias,
  * no ReLU) on the output gradient gives the input gradient. */

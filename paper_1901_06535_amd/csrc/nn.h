@@ -20,8 +20,24 @@ struct ConvArgs {
     int ldx, ldy;
     int N, H, W;
     int cin, cout, cout_store;
+    // Input stages fused into the loads (off by default):
+    //  * upsampled prefix: channels [0, up_c) come from `xu` (pixel stride
+    //    ldu, image (H/2) x (W/2)) by nearest 2x upsampling, the rest from x;
+    //  * stepper planes: the input is built from fp32 planes u, v, phi (row
+    //    pitch `ppitch`, image n at n * pplane): channels bf16(su u),
+    //    bf16(sv v), bf16(sp phi), zeros up to cin; x is not read.
+    const __bf16* xu = nullptr;
+    int ldu = 0, up_c = 0;
+    const float* pu = nullptr;
+    const float* pv = nullptr;
+    const float* pphi = nullptr;
+    int64_t ppitch = 0, pplane = 0;
+    float su = 0.0f, sv = 0.0f, sp = 0.0f;
 };
 hipError_t conv3x3(const ConvArgs& a, bool relu, bool bias, hipStream_t s);
+// The fused-input forms (bias and ReLU always applied; cout in {32, 64, 128}).
+hipError_t conv3x3_up(const ConvArgs& a, hipStream_t s);
+hipError_t conv3x3_planes(const ConvArgs& a, hipStream_t s);
 
 // Weight gradient of the same convolution: grad[9][cout][cin] (fp32) from
 // x (stride ldx) and dy (stride lddy); `part` is scratch of

@@ -96,7 +96,12 @@ constexpr int conv_pass_blocks() { return NB % 2 == 0 ? 2 : 1; }
 
 __device__ __forceinline__ int conv_slot(int row, int slot) { return slot ^ ((row >> RDC_CONV_SWZ_SHIFT) & 3); }
 
-template <int NBP, int PASSES, int P, bool RELU, bool BIAS>
+// Where the producers take the input from (ConvArgs): the x tensor, an
+// upsampled prefix of channels from xu and the rest from x, or the stepper
+// planes.
+enum ConvSrc { kSrcX = 0, kSrcUp = 1, kSrcPlanes = 2 };
+
+template <int NBP, int PASSES, int P, bool RELU, bool BIAS, int SRC>
 __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_tiles, int runs,
                                                           int run_len) {
     constexpr int CT = 32 * P + 2;                       // staged columns
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
         const int c0 = (s % chunks) * kConvKc;
         const int n = t / row_tiles;
         const int y0 = (t % row_tiles) * kConvRows;
-        const __bf16* X = a.x + (int64_t)n * a.H * a.W * a.ldx;
+        const __bf16* X = SRC == kSrcPlanes ? nullptr : a.x + (int64_t)n * a.H * a.W * a.ldx;
         const int tid = threadIdx.x - kConvRows * 64;
         __bf16* bx = xin + (s & 1) * kXin;
         __bf16* bw = wts + (s & 1) * kWts;
@@ -155,31 +160,87 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
                 vw[k] = ok ? ld : zero8();
             }
         };
+        // Upsampled prefix: this stage's 32 channels all come from xu (up_c
+        // is a multiple of 32), pixel (y, x) from xu's pixel (y/2, x/2).
+        const bool from_up = SRC == kSrcUp && c0 < a.up_c;
+        // Stepper planes (one 32-channel chunk): only each pixel's first
+        // 16-byte slot (channels 0..7) carries data, so the producers take one
+        // pixel per thread, load u, v, phi as coalesced 4-byte words and
+        // write that slot; the other three slots hold zeros, written once per
+        // buffer (stages 0 and 1).
+        constexpr int kPixT = RT * CT;
+        constexpr int kPerP = SRC == kSrcPlanes ? (kPixT + kPT - 1) / kPT : 1;
+        float fu[kPerP], fv[kPerP], fp[kPerP];
+        if constexpr (SRC == kSrcPlanes) {
 #pragma unroll
-        for (int k = 0; k < kPerX; ++k) {
-            const int i = tid + k * kPT;
-            const int q = i & 3;
-            const int pc = min(i >> 2, RT * CT - 1);
-            const int r = pc / CT, c = pc - (pc / CT) * CT;
-            const int yy = y0 - 1 + r, xx = x0 - 1 + c;
-            const int ch = c0 + 8 * q;
-            const bool ok = i < kPiecesX && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W &&
-                            ch < a.cin;
-            const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
-            const bf16x8 ld = load8(X + ((int64_t)yc * a.W + xc) * a.ldx + (ch < a.cin ? ch : 0));
-            vx[k] = ok ? ld : zero8();
+            for (int k = 0; k < kPerP; ++k) {
+                const int pc = min(tid + k * kPT, kPixT - 1);
+                const int r = pc / CT, c = pc - (pc / CT) * CT;
+                const int yc = min(max(y0 - 1 + r, 0), a.H - 1);
+                const int xc = min(max(x0 - 1 + c, 0), a.W - 1);
+                const int64_t o = n * a.pplane + (int64_t)yc * a.ppitch + xc;
+                fu[k] = a.pu[o];
+                fv[k] = a.pv[o];
+                fp[k] = a.pphi[o];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPerX; ++k) {
+                const int i = tid + k * kPT;
+                const int q = i & 3;
+                const int pc = min(i >> 2, RT * CT - 1);
+                const int r = pc / CT, c = pc - (pc / CT) * CT;
+                const int yy = y0 - 1 + r, xx = x0 - 1 + c;
+                const int ch = c0 + 8 * q;
+                const bool ok = i < kPiecesX && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W &&
+                                ch < a.cin;
+                const int yc = min(max(yy, 0), a.H - 1), xc = min(max(xx, 0), a.W - 1);
+                bf16x8 ld;
+                if (from_up) {
+                    const int hw = a.W >> 1;
+                    ld = load8(a.xu +
+                               (((int64_t)n * (a.H >> 1) + (yc >> 1)) * hw + (xc >> 1)) * a.ldu + ch);
+                } else {
+                    ld = load8(X + ((int64_t)yc * a.W + xc) * a.ldx + (ch < a.cin ? ch : 0));
+                }
+                vx[k] = ok ? ld : zero8();
+            }
         }
         // One latency phase when the registers allow it (one channel block
         // per pass); two otherwise.
         if constexpr (NBP == 1) {
             if (need_w) load_w();
         }
+        if constexpr (SRC == kSrcPlanes) {
 #pragma unroll
-        for (int k = 0; k < kPerX; ++k) {
-            const int i = tid + k * kPT;
-            if (i < kPiecesX)
-                *reinterpret_cast<bf16x8*>(&bx[(i >> 2) * kConvPix + 8 * conv_slot(i >> 2, i & 3)]) =
-                    vx[k];
+            for (int k = 0; k < kPerP; ++k) {
+                const int p = tid + k * kPT;
+                if (p < kPixT) {
+                    const int r = p / CT, c = p - (p / CT) * CT;
+                    const int yy = y0 - 1 + r, xx = x0 - 1 + c;
+                    bf16x8 val = zero8();
+                    if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+                        val[0] = f2bf(a.su * fu[k]);
+                        val[1] = f2bf(a.sv * fv[k]);
+                        val[2] = f2bf(a.sp * fp[k]);
+                    }
+                    *reinterpret_cast<bf16x8*>(&bx[p * kConvPix + 8 * conv_slot(p, 0)]) = val;
+                    if (s < 2) {
+#pragma unroll
+                        for (int q = 1; q < 4; ++q)
+                            *reinterpret_cast<bf16x8*>(&bx[p * kConvPix + 8 * conv_slot(p, q)]) =
+                                zero8();
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kPerX; ++k) {
+                const int i = tid + k * kPT;
+                if (i < kPiecesX)
+                    *reinterpret_cast<bf16x8*>(
+                        &bx[(i >> 2) * kConvPix + 8 * conv_slot(i >> 2, i & 3)]) = vx[k];
+            }
         }
         if constexpr (NBP != 1) {
             if (need_w) load_w();
@@ -816,7 +877,7 @@ inline unsigned grid_for(int64_t n, int block = 256) {
     return (unsigned)(g < 16384 ? (g > 0 ? g : 1) : 16384);
 }
 
-template <int NB, bool RELU, bool BIAS>
+template <int NB, bool RELU, bool BIAS, int SRC = kSrcX>
 hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
     constexpr int P = conv_pixel_blocks<NB>();
     constexpr int NBP = conv_pass_blocks<NB>();
@@ -838,7 +899,7 @@ hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
     runs = runs < 1 ? 1 : (runs > total_tiles ? total_tiles : runs);
     const int run_len = (total_tiles + runs - 1) / runs;
     runs = (total_tiles + run_len - 1) / run_len;
-    hipLaunchKernelGGL((k_conv3x3<NBP, NB / NBP, P, RELU, BIAS>), dim3(strips * runs),
+    hipLaunchKernelGGL((k_conv3x3<NBP, NB / NBP, P, RELU, BIAS, SRC>), dim3(strips * runs),
                        dim3(kConvThreads), 0, s, a, row_tiles, runs, run_len);
     return hipGetLastError();
 }
@@ -861,6 +922,24 @@ hipError_t conv3x3(const ConvArgs& a, bool relu, bool bias, hipStream_t s) {
         case 4: return conv_nb<4>(a, relu, bias, s);
         case 6: return conv_nb<6>(a, relu, bias, s);
         case 8: return conv_nb<8>(a, relu, bias, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t conv3x3_up(const ConvArgs& a, hipStream_t s) {
+    switch (a.cout >> 5) {
+        case 1: return conv_launch<1, true, true, kSrcUp>(a, s);
+        case 2: return conv_launch<2, true, true, kSrcUp>(a, s);
+        case 4: return conv_launch<4, true, true, kSrcUp>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t conv3x3_planes(const ConvArgs& a, hipStream_t s) {
+    switch (a.cout >> 5) {
+        case 1: return conv_launch<1, true, true, kSrcPlanes>(a, s);
+        case 2: return conv_launch<2, true, true, kSrcPlanes>(a, s);
+        case 4: return conv_launch<4, true, true, kSrcPlanes>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

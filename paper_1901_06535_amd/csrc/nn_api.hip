@@ -60,6 +60,80 @@ rdc_status rdc_nn_conv3x3(const void* x, int32_t ldx, const void* w, const float
     return nhip(rdc::nn::conv3x3(a, relu != 0, bias != nullptr, S(stream)));
 }
 
+rdc_status rdc_nn_conv3x3_up(const void* x, int32_t ldx, const void* xu, int32_t ldu,
+                             int32_t up_c, const void* w, const float* bias, void* y,
+                             int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
+                             int32_t cout, int32_t cout_store, void* stream) {
+    if (!x || !xu || !w || !bias || !y) return nfail("NULL tensor or bias");
+    if (n < 1 || n > 65535 || h < 2 || h > 262140 || h % 2 || wd < 64 || wd % 64)
+        return nfail("need 1 <= n <= 65535, even 2 <= h <= 262140 and w a multiple of 64");
+    if (cin < 32 || cin % 16 || up_c < 32 || up_c % 32 || up_c > cin ||
+        !(cout == 32 || cout == 64 || cout == 128))
+        return nfail("need cin % 16 == 0, up_c a multiple of 32 in 32..cin, cout in {32, 64, 128}");
+    if (cout_store < 1 || cout_store > cout) return nfail("cout_store must be in 1..cout");
+    if (ldx < cin || ldx % 8 || ldu < up_c || ldu % 8 || ldy < ((cout_store + 3) & ~3) ||
+        ldy % 4)
+        return nfail("strides: ldx >= cin, ldu >= up_c, both % 8 == 0; ldy >= cout_store rounded to 4, % 4 == 0");
+    if (!al16(x) || !al16(xu) || !al16(w) || !al8(y))
+        return nfail("x, xu, w need 16-byte and y 8-byte alignment");
+    rdc::nn::ConvArgs a;
+    a.x = static_cast<const __bf16*>(x);
+    a.w = static_cast<const __bf16*>(w);
+    a.bias = bias;
+    a.y = static_cast<__bf16*>(y);
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.N = n;
+    a.H = h;
+    a.W = wd;
+    a.cin = cin;
+    a.cout = cout;
+    a.cout_store = cout_store;
+    a.xu = static_cast<const __bf16*>(xu);
+    a.ldu = ldu;
+    a.up_c = up_c;
+    return nhip(rdc::nn::conv3x3_up(a, S(stream)));
+}
+
+rdc_status rdc_nn_conv3x3_planes(const float* u, const float* v, const float* phi,
+                                 int64_t pitch, int64_t plane_stride, float su, float sv,
+                                 float sp, const void* w, const float* bias, void* y, int32_t ldy,
+                                 int32_t n, int32_t h, int32_t wd, int32_t cin, int32_t cout,
+                                 int32_t cout_store, void* stream) {
+    if (!u || !v || !phi || !w || !bias || !y) return nfail("NULL plane, tensor or bias");
+    if (n < 1 || n > 65535 || h < 1 || h > 262140 || wd < 32 || wd % 32)
+        return nfail("need 1 <= n <= 65535, 1 <= h <= 262140 and w a multiple of 32");
+    if (pitch < wd || plane_stride < pitch * h) return nfail("need pitch >= w, plane_stride >= pitch*h");
+    if (!(cin == 16 || cin == 32) || !(cout == 32 || cout == 64 || cout == 128))
+        return nfail("need cin in {16, 32}, cout in {32, 64, 128}");
+    if (cout_store < 1 || cout_store > cout) return nfail("cout_store must be in 1..cout");
+    if (ldy < ((cout_store + 3) & ~3) || ldy % 4)
+        return nfail("ldy >= cout_store rounded to 4, ldy % 4 == 0");
+    if (!al16(w) || !al8(y)) return nfail("w needs 16-byte and y 8-byte alignment");
+    rdc::nn::ConvArgs a;
+    a.x = nullptr;
+    a.w = static_cast<const __bf16*>(w);
+    a.bias = bias;
+    a.y = static_cast<__bf16*>(y);
+    a.ldx = cin;
+    a.ldy = ldy;
+    a.N = n;
+    a.H = h;
+    a.W = wd;
+    a.cin = cin;
+    a.cout = cout;
+    a.cout_store = cout_store;
+    a.pu = u;
+    a.pv = v;
+    a.pphi = phi;
+    a.ppitch = pitch;
+    a.pplane = plane_stride;
+    a.su = su;
+    a.sv = sv;
+    a.sp = sp;
+    return nhip(rdc::nn::conv3x3_planes(a, S(stream)));
+}
+
 rdc_status rdc_nn_dgrad_weights(const float* w, void* wd, int32_t cout, int32_t cin,
                                 void* stream) {
     if (!w || !wd || cout < 1 || cin < 1) return nfail("bad dgrad weight arguments");

@@ -228,6 +228,60 @@ def forward(net: UNet, ws: Workspace, events=None) -> None:
     conv("head", at("d0b"), at("head"), relu=False)
 
 
+def forward_planes(net: UNet, ws: Workspace, u, v, phi, pitch, plane_stride,
+                   events=None) -> None:
+    """Inference form of prep + forward, leaving the same ws.a['head'] bit for
+    bit: the first layer builds its input from the stepper planes while
+    loading them (no x0), and each decoder layer reads the upsampled half of
+    its concatenation straight from the coarser level (no up2 writes).  The
+    concatenation buffers then hold only their skip channels, so training
+    (whose backward pass reads them whole) uses prep + forward."""
+    A, s = ws.a, net.stream.cuda_stream
+    at = lambda n, o=0: ws.at(A, n, o)
+    N = ws.N
+    (H, W), (H1, W1), (H2, W2), _ = (ws.shape[i] for i in range(4))
+
+    def timed(name, launch):
+        if events is not None:
+            e0 = net.torch.cuda.Event(enable_timing=True)
+            e1 = net.torch.cuda.Event(enable_timing=True)
+            e0.record(net.stream)
+        launch()
+        if events is not None:
+            e1.record(net.stream)
+            events.setdefault(name, []).append((e0, e1))
+
+    def conv(name, src, dst, relu=True):
+        _conv(net, ws, name, src, dst, relu=relu, events=events)
+
+    def up_conv(name, skip, low, up_c, dst, h, w):
+        cin, cout = [(ci, co) for n, ci, co, _ in LAYERS if n == name][0]
+        timed(name, lambda: rdc.nn("conv3x3_up", skip[0], skip[1], low[0], low[1], up_c,
+                                   net.w_ptr(name), net.b_ptr(name), dst[0], dst[1], N, h, w,
+                                   cin, cout, cout, s))
+
+    timed("e0a", lambda: rdc.nn("conv3x3_planes", u, v, phi, pitch, plane_stride, SU, SV, SP,
+                                net.w_ptr("e0a"), net.b_ptr("e0a"), *at("e0a"), N, H, W, IN_C,
+                                32, 32, s))
+    conv("e0b", at("e0a"), at("c0", 64))
+    rdc.nn("pool2", *at("c0", 64), *at("p1"), N, H1, W1, 32, s)
+    conv("e1a", at("p1"), at("e1a"))
+    conv("e1b", at("e1a"), at("c1", 128))
+    rdc.nn("pool2", *at("c1", 128), *at("p2"), N, H2, W2, 64, s)
+    conv("e2a", at("p2"), at("e2a"))
+    conv("e2b", at("e2a"), at("c2", 128))
+    rdc.nn("pool2", *at("c2", 128), *at("p3"), N, H2 // 2, W2 // 2, 128, s)
+    conv("b3a", at("p3"), at("b3a"))
+    conv("b3b", at("b3a"), at("b3b"))
+    up_conv("d2a", at("c2"), at("b3b"), 128, at("d2a"), H2, W2)
+    conv("d2b", at("d2a"), at("d2b"))
+    up_conv("d1a", at("c1"), at("d2b"), 128, at("d1a"), H1, W1)
+    conv("d1b", at("d1a"), at("d1b"))
+    up_conv("d0a", at("c0"), at("d1b"), 64, at("d0a"), H, W)
+    conv("d0b", at("d0a"), at("d0b"))
+    conv("head", at("d0b"), at("head"), relu=False)
+
+
 def _layer_bwd(net, ws, name, x, gy, gx=None):
     """Gradients of layer `name`: x = its input (addr, ld), gy = output
     gradient (addr, ld) (already through the ReLU adjoint).  Writes dW, db
@@ -575,9 +629,8 @@ class CoarseStepper:
 
     def _network_step(self):
         u, v = self.sim.current()
-        prep(self.net, self.ws, u.data_ptr(), v.data_ptr(), self.sim.planes[4].data_ptr(),
-             self.pitch, self.plane)
-        forward(self.net, self.ws)
+        forward_planes(self.net, self.ws, u.data_ptr(), v.data_ptr(),
+                       self.sim.planes[4].data_ptr(), self.pitch, self.plane)
         apply(self.net, self.ws, u.data_ptr(), v.data_ptr(), self.sim.planes[4].data_ptr(),
               u.data_ptr(), v.data_ptr(), self.pitch, self.plane, self.params)
 

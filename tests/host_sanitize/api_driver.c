@@ -299,6 +299,16 @@ static void nn(void) {
                        4.0f, partial, NULL) == RDC_OK);
     float *m = dev(100 * 4), *vv = dev(100 * 4);
     EXPECT(rdc_nn_adam(wf, grad, m, vv, 100, 1e-3f, 0.9f, 0.999f, 1e-8f, 1.0f, NULL) == RDC_OK);
+    EXPECT(rdc_nn_conv3x3_planes(u, v, phi, pitch, plane, 1.0f, 4.0f, 5.0f, wt, bias, y, cout,
+                                 n, h, w, cin, cout, cout, NULL) == RDC_OK);
+    EXPECT(rdc_nn_conv3x3_planes(u, v, phi, pitch, plane - 1, 1.0f, 4.0f, 5.0f, wt, bias, y,
+                                 cout, n, h, w, cin, cout, cout, NULL) == RDC_E_INVAL);
+    void *xcat = dev(px * 96 * 2), *xlow = dev(px / 4 * 64 * 2), *w96 = dev(9 * 96 * 32 * 2);
+    EXPECT(rdc_nn_conv3x3_up(xcat, 96, xlow, 64, 64, w96, bias, y, 32, n, h, w, 96, 32, 32,
+                             NULL) == RDC_OK);
+    EXPECT(rdc_nn_conv3x3_up(xcat, 96, xlow, 64, 64, w96, bias, y, 32, n, h - 1, w, 96, 32, 32,
+                             NULL) == RDC_E_INVAL);
+    hipFree(xcat); hipFree(xlow); hipFree(w96);
     uint32_t *cnt = dev(4);
     EXPECT(rdc_nn_front_check(u, uo, pitch, w, h, 0.5f, cnt, NULL) == RDC_OK);
     EXPECT(rdc_nn_state_check(u, v, phi, pitch, w, h, -0.002f, 1.5f, 1.4f, 0.3f, cnt, NULL) ==

@@ -174,3 +174,18 @@ def test_nn_argument_checks(lib):
                                   None) == rdc.RDC_E_INVAL
     assert lib.rdc_nn_adam(None, FAKE, FAKE, FAKE, 10, 1e-3, 0.9, 0.999, 1e-8, 1.0,
                            None) == rdc.RDC_E_INVAL
+    # fused-input convolutions: upsampling needs an even height and a whole
+    # 32-channel prefix; both need a bias and cout in {32, 64, 128}
+    up = lambda h, up_c, cout, bias=FAKE: lib.rdc_nn_conv3x3_up(
+        FAKE, 96, FAKE, 64, up_c, FAKE, bias, FAKE, cout, 1, h, 64, 96, cout, cout, None)
+    assert up(5, 64, 32) == rdc.RDC_E_INVAL and "even" in _nn_err(lib)
+    assert up(4, 48, 32) == rdc.RDC_E_INVAL
+    assert up(4, 128, 32) == rdc.RDC_E_INVAL         # prefix longer than cin
+    assert up(4, 64, 96) == rdc.RDC_E_INVAL
+    assert up(4, 64, 32, bias=None) == rdc.RDC_E_INVAL
+    planes = lambda pitch, stride, cout: lib.rdc_nn_conv3x3_planes(
+        FAKE, FAKE, FAKE, pitch, stride, 1.0, 4.0, 5.0, FAKE, FAKE, FAKE, cout, 1, 4, 64, 32,
+        cout, cout, None)
+    assert planes(32, 4096, 32) == rdc.RDC_E_INVAL    # pitch < w
+    assert planes(64, 100, 32) == rdc.RDC_E_INVAL     # images overlap
+    assert planes(64, 256, 256) == rdc.RDC_E_INVAL

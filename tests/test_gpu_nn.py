@@ -435,3 +435,75 @@ def test_network_is_translation_equivariant_in_x(torch):
     a = heads[0][:, :, 72:176]
     b = heads[1][:, :, 80:184]
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("cin,up_c,cout,N,H,W", [(96, 64, 32, 2, 6, 64), (192, 128, 64, 1, 4, 128),
+                                                 (256, 128, 128, 1, 4, 64), (64, 64, 32, 1, 2, 64)])
+def test_conv_with_upsampled_prefix_equals_up2_then_conv(torch, cin, up_c, cout, N, H, W):
+    """Reading the upsampled channels from the coarse level inside the
+    convolution's loads gives the same bits as writing them with up2 first."""
+    rng = np.random.default_rng(cin + up_c + cout)
+    ldx = cin
+    x, _ = _bf(torch, rng.standard_normal((N, H, W, ldx)))
+    low, _ = _bf(torch, rng.standard_normal((N, H // 2, W // 2, up_c)))
+    w, _ = _bf(torch, rng.standard_normal((9, cout, cin)) / np.sqrt(9 * cin))
+    b = torch.as_tensor(rng.standard_normal(cout).astype(np.float32)).cuda()
+    s = _stream(torch)
+    y_fused = torch.full((N, H, W, cout), 7.0, dtype=torch.bfloat16, device="cuda")
+    rdc.nn("conv3x3_up", x.data_ptr(), ldx, low.data_ptr(), up_c, up_c, w.data_ptr(),
+           b.data_ptr(), y_fused.data_ptr(), cout, N, H, W, cin, cout, cout, s)
+    xc = x.clone()
+    rdc.nn("up2", low.data_ptr(), up_c, xc.data_ptr(), ldx, N, H, W, up_c, s)
+    y_ref = torch.full((N, H, W, cout), 7.0, dtype=torch.bfloat16, device="cuda")
+    rdc.nn("conv3x3", xc.data_ptr(), ldx, w.data_ptr(), b.data_ptr(), y_ref.data_ptr(), cout,
+           N, H, W, cin, cout, cout, 1, s)
+    _sync(torch)
+    assert torch.equal(y_fused, y_ref)
+    assert (y_ref.float() > 0).any()
+    with pytest.raises(rdc.RdcError):                # odd height cannot be upsampled
+        rdc.nn("conv3x3_up", x.data_ptr(), ldx, low.data_ptr(), up_c, up_c, w.data_ptr(),
+               b.data_ptr(), y_fused.data_ptr(), cout, N, H - 1, W, cin, cout, cout, s)
+
+
+def test_conv_from_planes_equals_prep_then_conv(torch):
+    """Building the first layer's input from the stepper planes inside the
+    convolution's loads gives the same bits as prep followed by conv3x3."""
+    from paper_1901_06535_amd import surrogate as sg
+    N, H, W, cout = 2, 5, 96, 32
+    pitch, u, v, phi = _planes(torch, N, H, W, 71)
+    d = [torch.as_tensor(a).cuda() for a in (u, v, phi)]
+    plane = H * pitch
+    rng = np.random.default_rng(3)
+    w, _ = _bf(torch, rng.standard_normal((9, cout, sg.IN_C)) / np.sqrt(9 * 3))
+    b = torch.as_tensor(rng.standard_normal(cout).astype(np.float32)).cuda()
+    s = _stream(torch)
+    y_fused = torch.full((N, H, W, cout), 7.0, dtype=torch.bfloat16, device="cuda")
+    rdc.nn("conv3x3_planes", *(t.data_ptr() for t in d), pitch, plane, sg.SU, sg.SV, sg.SP,
+           w.data_ptr(), b.data_ptr(), y_fused.data_ptr(), cout, N, H, W, sg.IN_C, cout, cout, s)
+    x0 = torch.empty((N, H, W, sg.IN_C), dtype=torch.bfloat16, device="cuda")
+    rdc.nn("prep", *(t.data_ptr() for t in d), pitch, plane, x0.data_ptr(), sg.IN_C, N, H, W,
+           sg.SU, sg.SV, sg.SP, s)
+    y_ref = torch.full((N, H, W, cout), 7.0, dtype=torch.bfloat16, device="cuda")
+    rdc.nn("conv3x3", x0.data_ptr(), sg.IN_C, w.data_ptr(), b.data_ptr(), y_ref.data_ptr(), cout,
+           N, H, W, sg.IN_C, cout, cout, 1, s)
+    _sync(torch)
+    assert torch.equal(y_fused, y_ref)
+
+
+def test_inference_forward_equals_prep_and_forward(torch):
+    """The coarse stepper's inference forward (first layer from the planes,
+    decoders reading the coarse level) leaves the same head, bit for bit, as
+    prep + the training forward."""
+    sg, net, _ = _net(torch, seed=9)
+    N, H, W = 2, 16, 256
+    pitch, u, v, phi = _planes(torch, N, H, W, 81)
+    d = [torch.as_tensor(a).cuda() for a in (u, v, phi)]
+    plane = H * pitch
+    ws1 = sg.Workspace(net, N, H, W, train=False)
+    sg.prep(net, ws1, *(t.data_ptr() for t in d), pitch, plane)
+    sg.forward(net, ws1)
+    ws2 = sg.Workspace(net, N, H, W, train=False)
+    sg.forward_planes(net, ws2, *(t.data_ptr() for t in d), pitch, plane)
+    _sync(torch)
+    assert torch.equal(ws1.a["head"], ws2.a["head"])
+    assert ws1.a["head"].float().abs().max() > 0
