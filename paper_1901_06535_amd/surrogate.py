@@ -177,6 +177,28 @@ def conv_flops(name: str, ws: "Workspace") -> int:
     return 2 * 9 * cin * cout * H * W * ws.N
 
 
+UP_PREFIX = {"d2a": 128, "d1a": 128, "d0a": 64}   # upsampled channels of a decoder's input
+
+
+def conv_bytes(name: str, ws: "Workspace") -> int:
+    """HBM bytes one launch of convolution `name` must move in the inference
+    form (forward_planes): its input read once (the first layer: the three
+    fp32 stepper planes; a decoder: the skip channels at full resolution and
+    the upsampled prefix at the coarse level), its output written once, and
+    its bf16 weights."""
+    cin, cout = [(ci, co) for n, ci, co, _ in LAYERS if n == name][0]
+    H, W = ws._hw(name)
+    px = ws.N * H * W
+    if name == "e0a":
+        x = px * 12
+    elif name in UP_PREFIX:
+        up = UP_PREFIX[name]
+        x = px * (cin - up) * 2 + (px // 4) * up * 2
+    else:
+        x = px * cin * 2
+    return x + px * cout * 2 + 9 * cin * cout * 2
+
+
 def _conv(net, ws, name, src, dst, relu=True, store=None, events=None):
     """Forward convolution `name` from (addr, ld) src to (addr, ld) dst;
     with `events` (a dict), HIP events around the launch on the net's stream
@@ -273,11 +295,11 @@ def forward_planes(net: UNet, ws: Workspace, u, v, phi, pitch, plane_stride,
     rdc.nn("pool2", *at("c2", 128), *at("p3"), N, H2 // 2, W2 // 2, 128, s)
     conv("b3a", at("p3"), at("b3a"))
     conv("b3b", at("b3a"), at("b3b"))
-    up_conv("d2a", at("c2"), at("b3b"), 128, at("d2a"), H2, W2)
+    up_conv("d2a", at("c2"), at("b3b"), UP_PREFIX["d2a"], at("d2a"), H2, W2)
     conv("d2b", at("d2a"), at("d2b"))
-    up_conv("d1a", at("c1"), at("d2b"), 128, at("d1a"), H1, W1)
+    up_conv("d1a", at("c1"), at("d2b"), UP_PREFIX["d1a"], at("d1a"), H1, W1)
     conv("d1b", at("d1a"), at("d1b"))
-    up_conv("d0a", at("c0"), at("d1b"), 64, at("d0a"), H, W)
+    up_conv("d0a", at("c0"), at("d1b"), UP_PREFIX["d0a"], at("d0a"), H, W)
     conv("d0b", at("d0a"), at("d0b"))
     conv("head", at("d0b"), at("head"), relu=False)
 
