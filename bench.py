@@ -476,11 +476,13 @@ def bench_surrogate(args):
     # inference form the coarse stepper runs), and around each whole forward
     evs, whole = {}, []
     cu, cv = cs.sim.current()
+    uo, vo = torch.empty_like(cu), torch.empty_like(cv)
     for _ in range(5):
         w0, w1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         w0.record(net.stream)
         sg.forward_planes(net, cs.ws, cu.data_ptr(), cv.data_ptr(), cs.sim.planes[4].data_ptr(),
-                          cs.pitch, cs.plane, events=evs)
+                          cs.pitch, cs.plane, events=evs,
+                          predict=(uo.data_ptr(), vo.data_ptr(), wl.params))
         w1.record(net.stream)
         whole.append((w0, w1))
     torch.cuda.synchronize()

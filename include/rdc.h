@@ -323,6 +323,19 @@ rdc_status rdc_nn_conv3x3_planes(const float *u, const float *v, const float *ph
                                  int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
                                  int32_t cout, int32_t cout_store, void *stream);
 
+/* The network's head and the prediction in one launch: rdc_nn_conv3x3 with
+ * 32 output channels, bias, no ReLU, whose outputs are not stored; instead
+ * each pixel's first two (bf16-rounded) outputs go through rdc_nn_apply:
+ * uo = clamp(u + out0/su, 0, 1), vo = clamp(v + out1/sv, 0, (cmax - phi)/f)
+ * on the fp32 planes (row pitch `pitch`, image i at i*plane_stride).
+ * Bit-identical to rdc_nn_conv3x3 into a head tensor followed by
+ * rdc_nn_apply; uo, vo may alias u, v. */
+rdc_status rdc_nn_conv3x3_apply(const void *x, int32_t ldx, const void *w, const float *bias,
+                                const float *u, const float *v, const float *phi, int64_t pitch,
+                                int64_t plane_stride, float *uo, float *vo, int32_t n, int32_t h,
+                                int32_t wd, int32_t cin, float su, float sv, float f, float cmax,
+                                void *stream);
+
 /* Weights of the input-gradient convolution: wd[tap][ci][co] =
  * bf16(w[8 - tap][co][ci]); rdc_nn_conv3x3 with them (cin <-> cout, no bias,
  * no ReLU) on the output gradient gives the input gradient. */

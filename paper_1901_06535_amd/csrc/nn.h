@@ -33,11 +33,20 @@ struct ConvArgs {
     const float* pphi = nullptr;
     int64_t ppitch = 0, pplane = 0;
     float su = 0.0f, sv = 0.0f, sp = 0.0f;
+    // Prediction epilogue (conv3x3_apply): instead of storing the output,
+    // (uo, vo) = the apply kernel's projection of (u, v) + (out0 / su,
+    // out1 / sv) from the bf16-rounded first two output channels, on the
+    // planes pu, pv, pphi (layout ppitch, pplane).
+    float* uo = nullptr;
+    float* vo = nullptr;
+    float f = 0.0f, cmax = 0.0f;
 };
 hipError_t conv3x3(const ConvArgs& a, bool relu, bool bias, hipStream_t s);
 // The fused-input forms (bias and ReLU always applied; cout in {32, 64, 128}).
 hipError_t conv3x3_up(const ConvArgs& a, hipStream_t s);
 hipError_t conv3x3_planes(const ConvArgs& a, hipStream_t s);
+// cout = 32, bias, no ReLU, prediction epilogue (see ConvArgs).
+hipError_t conv3x3_apply(const ConvArgs& a, hipStream_t s);
 
 // Weight gradient of the same convolution: grad[9][cout][cin] (fp32) from
 // x (stride ldx) and dy (stride lddy); `part` is scratch of

@@ -100,8 +100,11 @@ __device__ __forceinline__ int conv_slot(int row, int slot) { return slot ^ ((ro
 // upsampled prefix of channels from xu and the rest from x, or the stepper
 // planes.
 enum ConvSrc { kSrcX = 0, kSrcUp = 1, kSrcPlanes = 2 };
+// What the consumers do with an output tile: store it, or (one 32-channel
+// block) apply the prediction to the stepper planes from its channels 0, 1.
+enum ConvEpi { kEpiStore = 0, kEpiApply = 1 };
 
-template <int NBP, int PASSES, int P, bool RELU, bool BIAS, int SRC>
+template <int NBP, int PASSES, int P, bool RELU, bool BIAS, int SRC, int EPI = kEpiStore>
 __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_tiles, int runs,
                                                           int run_len) {
     constexpr int CT = 32 * P + 2;                       // staged columns
@@ -325,8 +328,10 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         if (x0 + p * 32 >= a.W) continue;
-                        __bf16* Y = a.y + ((int64_t)n * a.H * a.W + (int64_t)y * a.W + x0 + p * 32 +
-                                           pl) * a.ldy;
+                        __bf16* Y = EPI == kEpiApply ? nullptr
+                                                     : a.y + ((int64_t)n * a.H * a.W +
+                                                              (int64_t)y * a.W + x0 + p * 32 + pl) *
+                                                                 a.ldy;
 #pragma unroll
                         for (int b = 0; b < NBP; ++b) {
 #pragma unroll
@@ -340,7 +345,20 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
                                     if (RELU) v = v > 0.0f ? v : 0.0f;
                                     out[i] = f2bf(v);
                                 }
-                                if (co < a.cout_store) {
+                                if constexpr (EPI == kEpiApply) {
+                                    // This lane holds channels 0..3 of pixel x: the
+                                    // apply kernel's arithmetic on the bf16 outputs.
+                                    if (co == 0) {
+                                        const int64_t o = n * a.pplane + (int64_t)y * a.ppitch +
+                                                          x0 + p * 32 + pl;
+                                        const float vcap =
+                                            fmaxf((a.cmax - a.pphi[o]) / a.f, 0.0f);
+                                        const float un = a.pu[o] + bf2f(out[0]) / a.su;
+                                        const float vn = a.pv[o] + bf2f(out[1]) / a.sv;
+                                        a.uo[o] = fminf(fmaxf(un, 0.0f), 1.0f);
+                                        a.vo[o] = fminf(fmaxf(vn, 0.0f), vcap);
+                                    }
+                                } else if (co < a.cout_store) {
                                     uint2 pk;
                                     pk.x = (uint32_t)__builtin_bit_cast(uint16_t, out[0]) |
                                            ((uint32_t)__builtin_bit_cast(uint16_t, out[1]) << 16);
@@ -877,7 +895,7 @@ inline unsigned grid_for(int64_t n, int block = 256) {
     return (unsigned)(g < 16384 ? (g > 0 ? g : 1) : 16384);
 }
 
-template <int NB, bool RELU, bool BIAS, int SRC = kSrcX>
+template <int NB, bool RELU, bool BIAS, int SRC = kSrcX, int EPI = kEpiStore>
 hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
     constexpr int P = conv_pixel_blocks<NB>();
     constexpr int NBP = conv_pass_blocks<NB>();
@@ -899,7 +917,7 @@ hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
     runs = runs < 1 ? 1 : (runs > total_tiles ? total_tiles : runs);
     const int run_len = (total_tiles + runs - 1) / runs;
     runs = (total_tiles + run_len - 1) / run_len;
-    hipLaunchKernelGGL((k_conv3x3<NBP, NB / NBP, P, RELU, BIAS, SRC>), dim3(strips * runs),
+    hipLaunchKernelGGL((k_conv3x3<NBP, NB / NBP, P, RELU, BIAS, SRC, EPI>), dim3(strips * runs),
                        dim3(kConvThreads), 0, s, a, row_tiles, runs, run_len);
     return hipGetLastError();
 }
@@ -942,6 +960,11 @@ hipError_t conv3x3_planes(const ConvArgs& a, hipStream_t s) {
         case 4: return conv_launch<4, true, true, kSrcPlanes>(a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t conv3x3_apply(const ConvArgs& a, hipStream_t s) {
+    if (a.cout != 32) return hipErrorInvalidValue;
+    return conv_launch<1, false, true, kSrcX, kEpiApply>(a, s);
 }
 
 hipError_t flip_weights(const float* w, __bf16* wd, int cout, int cin, hipStream_t s) {

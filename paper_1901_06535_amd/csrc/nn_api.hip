@@ -134,6 +134,46 @@ rdc_status rdc_nn_conv3x3_planes(const float* u, const float* v, const float* ph
     return nhip(rdc::nn::conv3x3_planes(a, S(stream)));
 }
 
+rdc_status rdc_nn_conv3x3_apply(const void* x, int32_t ldx, const void* w, const float* bias,
+                                const float* u, const float* v, const float* phi, int64_t pitch,
+                                int64_t plane_stride, float* uo, float* vo, int32_t n, int32_t h,
+                                int32_t wd, int32_t cin, float su, float sv, float f, float cmax,
+                                void* stream) {
+    if (!x || !w || !bias || !u || !v || !phi || !uo || !vo)
+        return nfail("NULL tensor, bias or plane");
+    if (n < 1 || n > 65535 || h < 1 || h > 262140 || wd < 32 || wd % 32)
+        return nfail("need 1 <= n <= 65535, 1 <= h <= 262140 and w a multiple of 32");
+    if (cin < 16 || cin % 16 || ldx < cin || ldx % 8) return nfail("need cin % 16 == 0, ldx >= cin, ldx % 8 == 0");
+    if (pitch < wd || plane_stride < pitch * h) return nfail("need pitch >= w, plane_stride >= pitch*h");
+    if (!(f > 0.0f) || !(su != 0.0f) || !(sv != 0.0f)) return nfail("need f > 0 and nonzero su, sv");
+    if (!al16(x) || !al16(w)) return nfail("x, w need 16-byte alignment");
+    rdc::nn::ConvArgs a;
+    a.x = static_cast<const __bf16*>(x);
+    a.w = static_cast<const __bf16*>(w);
+    a.bias = bias;
+    a.y = nullptr;
+    a.ldx = ldx;
+    a.ldy = 32;
+    a.N = n;
+    a.H = h;
+    a.W = wd;
+    a.cin = cin;
+    a.cout = 32;
+    a.cout_store = 32;
+    a.pu = u;
+    a.pv = v;
+    a.pphi = phi;
+    a.ppitch = pitch;
+    a.pplane = plane_stride;
+    a.su = su;
+    a.sv = sv;
+    a.uo = uo;
+    a.vo = vo;
+    a.f = f;
+    a.cmax = cmax;
+    return nhip(rdc::nn::conv3x3_apply(a, S(stream)));
+}
+
 rdc_status rdc_nn_dgrad_weights(const float* w, void* wd, int32_t cout, int32_t cin,
                                 void* stream) {
     if (!w || !wd || cout < 1 || cin < 1) return nfail("bad dgrad weight arguments");

@@ -34,6 +34,7 @@ EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_wr
            "rdc_batch_capture", "rdc_graph_launch", "rdc_graph_destroy", "rdc_batch_last_error",
            "rdc_batch_current",
            "rdc_nn_conv3x3", "rdc_nn_conv3x3_up", "rdc_nn_conv3x3_planes",
+           "rdc_nn_conv3x3_apply",
            "rdc_nn_dgrad_weights", "rdc_nn_wgrad_scratch_floats",
            "rdc_nn_conv3x3_wgrad", "rdc_nn_to_bf16", "rdc_nn_relu_bwd",
            "rdc_nn_pool2", "rdc_nn_pool2_bwd", "rdc_nn_up2", "rdc_nn_up2_bwd", "rdc_nn_prep",
@@ -116,6 +117,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_nn_conv3x3_planes": (i32, [vp, vp, vp, i64, i64, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, vp, vp, vp, i32, i32, i32, i32, i32, i32,
                                         i32, vp]),
+        "rdc_nn_conv3x3_apply": (i32, [vp, i32, vp, vp, vp, vp, vp, i64, i64, vp, vp, i32, i32,
+                                       i32, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, vp]),
         "rdc_nn_dgrad_weights": (i32, [vp, vp, i32, i32, vp]),
         "rdc_nn_wgrad_scratch_floats": (i64, [i32, i32, i32, i32, i32]),
         "rdc_nn_conv3x3_wgrad": (i32, [vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, i32, i32, vp]),

@@ -251,13 +251,15 @@ def forward(net: UNet, ws: Workspace, events=None) -> None:
 
 
 def forward_planes(net: UNet, ws: Workspace, u, v, phi, pitch, plane_stride,
-                   events=None) -> None:
+                   events=None, predict=None) -> None:
     """Inference form of prep + forward, leaving the same ws.a['head'] bit for
     bit: the first layer builds its input from the stepper planes while
     loading them (no x0), and each decoder layer reads the upsampled half of
     its concatenation straight from the coarser level (no up2 writes).  The
     concatenation buffers then hold only their skip channels, so training
-    (whose backward pass reads them whole) uses prep + forward."""
+    (whose backward pass reads them whole) uses prep + forward.  With
+    `predict` = (uo, vo, params) the head's launch also applies the
+    prediction (as `apply` would) and leaves ws.a['head'] untouched."""
     A, s = ws.a, net.stream.cuda_stream
     at = lambda n, o=0: ws.at(A, n, o)
     N = ws.N
@@ -301,7 +303,14 @@ def forward_planes(net: UNet, ws: Workspace, u, v, phi, pitch, plane_stride,
     conv("d1b", at("d1a"), at("d1b"))
     up_conv("d0a", at("c0"), at("d1b"), UP_PREFIX["d0a"], at("d0a"), H, W)
     conv("d0b", at("d0a"), at("d0b"))
-    conv("head", at("d0b"), at("head"), relu=False)
+    if predict is None:
+        conv("head", at("d0b"), at("head"), relu=False)
+    else:
+        uo, vo, params = predict
+        timed("head", lambda: rdc.nn("conv3x3_apply", *at("d0b"), net.w_ptr("head"),
+                                     net.b_ptr("head"), u, v, phi, pitch, plane_stride, uo, vo,
+                                     N, H, W, 32, SU, SV, float(params["f"]),
+                                     euler_safe_c(params), s))
 
 
 def _layer_bwd(net, ws, name, x, gy, gx=None):
@@ -652,9 +661,8 @@ class CoarseStepper:
     def _network_step(self):
         u, v = self.sim.current()
         forward_planes(self.net, self.ws, u.data_ptr(), v.data_ptr(),
-                       self.sim.planes[4].data_ptr(), self.pitch, self.plane)
-        apply(self.net, self.ws, u.data_ptr(), v.data_ptr(), self.sim.planes[4].data_ptr(),
-              u.data_ptr(), v.data_ptr(), self.pitch, self.plane, self.params)
+                       self.sim.planes[4].data_ptr(), self.pitch, self.plane,
+                       predict=(u.data_ptr(), v.data_ptr(), self.params))
 
     def _cells_off(self, a: "rdc.Sim", b: "rdc.Sim") -> int:
         """Cells whose fronts differ by more than one cell between a and b."""

@@ -309,6 +309,10 @@ static void nn(void) {
     EXPECT(rdc_nn_conv3x3_up(xcat, 96, xlow, 64, 64, w96, bias, y, 32, n, h - 1, w, 96, 32, 32,
                              NULL) == RDC_E_INVAL);
     hipFree(xcat); hipFree(xlow); hipFree(w96);
+    EXPECT(rdc_nn_conv3x3_apply(x, cin, wt, bias, u, v, phi, pitch, plane, uo, vo, n, h, w, cin,
+                                1.0f, 4.0f, 1.4f, 0.3f, NULL) == RDC_OK);
+    EXPECT(rdc_nn_conv3x3_apply(x, cin, wt, bias, u, v, phi, pitch, plane, uo, vo, n, h, w, cin,
+                                1.0f, 4.0f, 0.0f, 0.3f, NULL) == RDC_E_INVAL);
     uint32_t *cnt = dev(4);
     EXPECT(rdc_nn_front_check(u, uo, pitch, w, h, 0.5f, cnt, NULL) == RDC_OK);
     EXPECT(rdc_nn_state_check(u, v, phi, pitch, w, h, -0.002f, 1.5f, 1.4f, 0.3f, cnt, NULL) ==

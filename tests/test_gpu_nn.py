@@ -507,3 +507,30 @@ def test_inference_forward_equals_prep_and_forward(torch):
     _sync(torch)
     assert torch.equal(ws1.a["head"], ws2.a["head"])
     assert ws1.a["head"].float().abs().max() > 0
+
+
+def test_head_with_prediction_equals_head_then_apply(torch):
+    """The head launch that applies the prediction itself writes the same
+    (u, v) planes, bit for bit, as the head into a tensor followed by apply;
+    in place, as the coarse stepper runs it."""
+    sg, net, _ = _net(torch, seed=13)
+    N, H, W = 2, 16, 256
+    pitch, u, v, phi = _planes(torch, N, H, W, 91)
+    plane = H * pitch
+    params = inputs.PARAMS_WORKLOAD
+    d = [torch.as_tensor(a).cuda() for a in (u, v, phi)]
+    ws1 = sg.Workspace(net, N, H, W, train=False)
+    sg.forward_planes(net, ws1, *(t.data_ptr() for t in d), pitch, plane)
+    uo = torch.full_like(d[0], -7.0)
+    vo = torch.full_like(d[1], -7.0)
+    sg.apply(net, ws1, d[0].data_ptr(), d[1].data_ptr(), d[2].data_ptr(), uo.data_ptr(),
+             vo.data_ptr(), pitch, plane, params)
+    ws2 = sg.Workspace(net, N, H, W, train=False)
+    u2, v2 = d[0].clone(), d[1].clone()
+    sg.forward_planes(net, ws2, u2.data_ptr(), v2.data_ptr(), d[2].data_ptr(), pitch, plane,
+                      predict=(u2.data_ptr(), v2.data_ptr(), params))
+    _sync(torch)
+    c = lambda t: t[:, :, :W]
+    assert torch.equal(c(u2), c(uo)) and torch.equal(c(v2), c(vo))
+    assert not torch.equal(c(u2), c(d[0]))           # the prediction moved the state
+    assert torch.equal(u2[:, :, W:], d[0][:, :, W:])  # padding columns untouched
