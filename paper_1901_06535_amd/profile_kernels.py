@@ -21,7 +21,12 @@ on other sources) and printed as a table;
 
     python3 -m paper_1901_06535_amd.profile_kernels --stats KERNEL_STATS.csv
 
-prints the top rows of a rocprofv3 --stats kernel table.
+prints the top rows of a rocprofv3 --stats kernel table, and
+
+    python3 -m paper_1901_06535_amd.profile_kernels --valu COUNTERS.csv
+
+the VALU instruction counts and busy fraction of one --pmc run of the
+counters in VALU_COUNTERS.
 """
 from __future__ import annotations
 
@@ -83,6 +88,26 @@ def stats(path: str, top: int = 20) -> None:
         print("%-40s calls=%6d avg_us=%9.2f pct=%6.2f" % (name[:40], calls, avg / 1e3, pct))
 
 
+VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_INSTS_LDS", "GRBM_GUI_ACTIVE")
+
+
+def valu(path: str, cus: int = 256, xcds: int = 8) -> None:
+    """Per-dispatch averages of the VALU counters of one rocprofv3 --pmc run
+    (VALU_COUNTERS) for each stepper kernel, and the VALU busy fraction: a
+    wave64 VALU instruction occupies one SIMD16 for 4 cycles, so busy =
+    SQ_INSTS_VALU / (GRBM_GUI_ACTIVE / xcds * cus) (4 SIMDs x 1/4)."""
+    m = {c: _counter_means(path, c) for c in VALU_COUNTERS}
+    for k in sorted(m["SQ_INSTS_VALU"]):
+        if not k.startswith("k_step") and k != "k_copy16":
+            continue
+        g = lambda c: m[c].get(k, (float("nan"), 0))[0]
+        gui = g("GRBM_GUI_ACTIVE")
+        busy = g("SQ_INSTS_VALU") / (gui / xcds * cus) if gui > 0 else float("nan")
+        print("%-30s VALU_insts=%.4g waves=%.4g busy_cycles=%.4g gui=%.4g lds=%.4g -> VALU busy %.0f%%"
+              % (k, g("SQ_INSTS_VALU"), g("SQ_WAVES"), g("SQ_BUSY_CYCLES"), gui,
+                 g("SQ_INSTS_LDS"), 100 * busy))
+
+
 def summarize(fetch_csv: str, write_csv: str, out_json: str) -> None:
     f = _counter_means(fetch_csv, "FETCH_SIZE")
     w = _counter_means(write_csv, "WRITE_SIZE")
@@ -125,6 +150,7 @@ def main():
     ap.add_argument("--big", type=int, default=16384)
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--stats", metavar="KERNEL_STATS_CSV")
+    ap.add_argument("--valu", metavar="COUNTER_CSV")
     ap.add_argument("--top", type=int, default=20)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "profiles",
                                                   "traffic.json"))
@@ -133,6 +159,8 @@ def main():
         return summarize(args.summarize[0], args.summarize[1], args.out)
     if args.stats:
         return stats(args.stats, args.top)
+    if args.valu:
+        return valu(args.valu)
     log = []
     wl = inputs.circuit(n=args.n, seed=1002, steps=10000, ndisks=256)
     sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
