@@ -534,3 +534,37 @@ def test_head_with_prediction_equals_head_then_apply(torch):
     assert torch.equal(c(u2), c(uo)) and torch.equal(c(v2), c(vo))
     assert not torch.equal(c(u2), c(d[0]))           # the prediction moved the state
     assert torch.equal(u2[:, :, W:], d[0][:, :, W:])  # padding columns untouched
+
+
+def test_inference_step_at_full_size_equals_unfused_route(torch):
+    """At the coarse stepper's full size (one 2048^2 grid), the inference step
+    (planes input, upsampled prefixes, prediction in the head's epilogue)
+    gives the same (u, v), bit for bit, as prep + forward + apply."""
+    sg, net, _ = _net(torch, seed=17)
+    N, H, W = 1, 2048, 2048
+    wl = inputs.circuit(n=2048, seed=1005, steps=100, ndisks=8)
+    pitch = rdc.pitch_for(W)
+    planes = []
+    for a in (wl.u0, wl.v0, wl.phi):
+        t = torch.zeros((H, pitch), dtype=torch.float32, device="cuda")
+        t[:, :W] = torch.as_tensor(a).cuda()
+        planes.append(t)
+    u, v, phi = planes
+    for s in wl.stimuli:                              # excite the disks so the head is non-trivial
+        yy, xx = torch.meshgrid(torch.arange(H, device="cuda"), torch.arange(W, device="cuda"),
+                                indexing="ij")
+        u[:, :W][(yy - s.cy) ** 2 + (xx - s.cx) ** 2 <= s.r ** 2] = 1.0
+    plane = H * pitch
+    params = wl.params
+    ws = sg.Workspace(net, N, H, W, train=False)
+    sg.prep(net, ws, u.data_ptr(), v.data_ptr(), phi.data_ptr(), pitch, plane)
+    sg.forward(net, ws)
+    uo, vo = torch.empty_like(u), torch.empty_like(v)
+    sg.apply(net, ws, u.data_ptr(), v.data_ptr(), phi.data_ptr(), uo.data_ptr(), vo.data_ptr(),
+             pitch, plane, params)
+    u2, v2 = u.clone(), v.clone()
+    sg.forward_planes(net, ws, u2.data_ptr(), v2.data_ptr(), phi.data_ptr(), pitch, plane,
+                      predict=(u2.data_ptr(), v2.data_ptr(), params))
+    _sync(torch)
+    assert torch.equal(u2[:, :W], uo[:, :W]) and torch.equal(v2[:, :W], vo[:, :W])
+    assert not torch.equal(u2[:, :W], u[:, :W])
