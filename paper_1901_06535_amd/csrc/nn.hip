@@ -104,7 +104,11 @@ enum ConvSrc { kSrcX = 0, kSrcUp = 1, kSrcPlanes = 2 };
 // block) apply the prediction to the stepper planes from its channels 0, 1.
 enum ConvEpi { kEpiStore = 0, kEpiApply = 1 };
 
-template <int NBP, int PASSES, int P, bool RELU, bool BIAS, int SRC, int EPI = kEpiStore>
+// WCH > 0: the weights of all WCH input-channel chunks (one pass) stay
+// resident in LDS, loaded once by the first WCH stages, instead of being
+// restaged with every stage.
+template <int NBP, int PASSES, int P, bool RELU, bool BIAS, int SRC, int EPI = kEpiStore,
+          int WCH = 0>
 __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_tiles, int runs,
                                                           int run_len) {
     constexpr int CT = 32 * P + 2;                       // staged columns
@@ -118,7 +122,8 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
     constexpr int kPerX = (kPiecesX + kPT - 1) / kPT;
     constexpr int kPerW = (kPiecesW + kPT - 1) / kPT;
     __shared__ __attribute__((aligned(16))) __bf16 xin[2 * kXin];
-    __shared__ __attribute__((aligned(16))) __bf16 wts[2 * kWts];
+    static_assert(WCH == 0 || PASSES == 1, "resident weights cover one pass");
+    __shared__ __attribute__((aligned(16))) __bf16 wts[(WCH > 0 ? WCH : 2) * kWts];
 
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool producer = wv >= kConvRows;
@@ -143,11 +148,11 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
         const __bf16* X = SRC == kSrcPlanes ? nullptr : a.x + (int64_t)n * a.H * a.W * a.ldx;
         const int tid = threadIdx.x - kConvRows * 64;
         __bf16* bx = xin + (s & 1) * kXin;
-        __bf16* bw = wts + (s & 1) * kWts;
+        __bf16* bw = wts + (WCH > 0 ? s % chunks : (s & 1)) * kWts;
         // The weights depend only on (pass, chunk): with one stage per tile
         // they are the same for every stage, and both buffers are filled by
         // the first two stages.
-        const bool need_w = per_tile > 1 || s < 2;
+        const bool need_w = WCH > 0 ? s < chunks : (per_tile > 1 || s < 2);
         bf16x8 vx[kPerX], vw[kPerW];
         auto load_w = [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3x3(ConvArgs a, int row_ti
     for (int s = 0; s < stages; ++s) {
         {
             const __bf16* bx = xin + (s & 1) * kXin;
-            const __bf16* bw = wts + (s & 1) * kWts;
+            const __bf16* bw = wts + (WCH > 0 ? s % chunks : (s & 1)) * kWts;
             // Taps unrolled in groups small enough to keep the operands of
             // the taps in flight within the register budget of 3 waves/SIMD.
             constexpr int kTapUnroll = NBP == 1 ? 3 : 1;
@@ -895,7 +900,7 @@ inline unsigned grid_for(int64_t n, int block = 256) {
     return (unsigned)(g < 16384 ? (g > 0 ? g : 1) : 16384);
 }
 
-template <int NB, bool RELU, bool BIAS, int SRC = kSrcX, int EPI = kEpiStore>
+template <int NB, bool RELU, bool BIAS, int SRC = kSrcX, int EPI = kEpiStore, int WCH = 0>
 hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
     constexpr int P = conv_pixel_blocks<NB>();
     constexpr int NBP = conv_pass_blocks<NB>();
@@ -917,13 +922,25 @@ hipError_t conv_launch(const ConvArgs& a, hipStream_t s) {
     runs = runs < 1 ? 1 : (runs > total_tiles ? total_tiles : runs);
     const int run_len = (total_tiles + runs - 1) / runs;
     runs = (total_tiles + run_len - 1) / run_len;
-    hipLaunchKernelGGL((k_conv3x3<NBP, NB / NBP, P, RELU, BIAS, SRC, EPI>), dim3(strips * runs),
+    if (WCH > 0 && (a.cin + kConvKc - 1) / kConvKc > WCH) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_conv3x3<NBP, NB / NBP, P, RELU, BIAS, SRC, EPI, WCH>), dim3(strips * runs),
                        dim3(kConvThreads), 0, s, a, row_tiles, runs, run_len);
     return hipGetLastError();
 }
 
 template <int NB>
 hipError_t conv_nb(const ConvArgs& a, bool relu, bool bias, hipStream_t s) {
+    // Layers whose one pass of weights fits the LDS the double buffer uses
+    // (32 outputs: up to 3 chunks; 64 outputs: 2 chunks) keep them resident.
+    const int chunks = (a.cin + kConvKc - 1) / kConvKc;
+    if constexpr (NB == 1) {
+        if (relu && bias && chunks >= 2 && chunks <= 3)
+            return conv_launch<NB, true, true, kSrcX, kEpiStore, 3>(a, s);
+    }
+    if constexpr (NB == 2) {
+        if (relu && bias && chunks == 2)
+            return conv_launch<NB, true, true, kSrcX, kEpiStore, 2>(a, s);
+    }
     if (relu && bias) return conv_launch<NB, true, true>(a, s);
     if (bias) return conv_launch<NB, false, true>(a, s);
     if (relu) return conv_launch<NB, true, false>(a, s);
@@ -946,7 +963,10 @@ hipError_t conv3x3(const ConvArgs& a, bool relu, bool bias, hipStream_t s) {
 
 hipError_t conv3x3_up(const ConvArgs& a, hipStream_t s) {
     switch (a.cout >> 5) {
-        case 1: return conv_launch<1, true, true, kSrcUp>(a, s);
+        case 1:   // 32 outputs: up to three 18 KB weight chunks stay in LDS
+            if (a.cin > kConvKc && a.cin <= 3 * kConvKc)
+                return conv_launch<1, true, true, kSrcUp, kEpiStore, 3>(a, s);
+            return conv_launch<1, true, true, kSrcUp>(a, s);
         case 2: return conv_launch<2, true, true, kSrcUp>(a, s);
         case 4: return conv_launch<4, true, true, kSrcUp>(a, s);
         default: return hipErrorInvalidValue;

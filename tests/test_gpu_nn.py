@@ -55,6 +55,8 @@ CONV_CASES = [  # cin, cout, N, H, W, relu, bias, cout_store, ldx extra channels
     (128, 256, 1, 2, 32, 0, 0, 256, 0),
     (64, 192, 1, 3, 32, 0, 0, 192, 0),
     (32, 32, 1, 4, 64, 0, 1, 4, 0),
+    (64, 64, 2, 5, 64, 1, 1, 64, 8),      # weights of both chunks resident in LDS
+    (64, 32, 1, 9, 96, 1, 1, 32, 0),      # 32 outputs, two resident chunks
 ]
 
 
