@@ -493,13 +493,13 @@ class Trainer:
             nb = 4 * self.batch * self.plane
             if self.prev_ok and self.rng.random() < self.pushforward:
                 # training input := the network's prediction of S_t from S_(t-K)
-                prep(self.net, self.ws, _ptr(self.u_prev), _ptr(self.v_prev), phi, self.pitch,
-                     self.plane)
-                forward(self.net, self.ws)
+                # (the inference form; the training forward below rewrites
+                # every buffer it reads)
                 rdc.rdc_copy(_ptr(self.u_next), u, nb, s)          # keep the plain S_t
                 rdc.rdc_copy(_ptr(self.v_next), v, nb, s)
-                apply(self.net, self.ws, _ptr(self.u_prev), _ptr(self.v_prev), phi, u, v,
-                      self.pitch, self.plane, self.wls[0].params)
+                forward_planes(self.net, self.ws, _ptr(self.u_prev), _ptr(self.v_prev), phi,
+                               self.pitch, self.plane,
+                               predict=(u, v, self.wls[0].params))
                 self.u_prev, self.u_next = self.u_next, self.u_prev
                 self.v_prev, self.v_next = self.v_next, self.v_prev
             else:
