@@ -73,6 +73,12 @@ __device__ __forceinline__ bf16x8 zero8() {
 // permuted by XOR with (r >> 2) & 3, so any 16 consecutive rows read at one
 // slot cover all 64 banks (gfx950 serves a 16-byte-per-lane LDS access 16
 // lanes at a time; hardware counters read zero bank conflicts with it).
+// Variants (template arguments): the producers may build the input while
+// loading it (SRC: an upsampled channel prefix read from the coarser level,
+// or the network input from the stepper's fp32 planes), the consumers may
+// apply the prediction instead of storing (EPI), and one pass of weights may
+// stay resident in LDS instead of being restaged with every stage (WCH).
+// Each variant computes the same bits as the unfused route.
 constexpr int kConvRows = 8;                      // output rows per tile = consumer waves
 constexpr int kConvProducers = 4;                 // producer waves
 constexpr int kConvThreads = (kConvRows + kConvProducers) * 64;
