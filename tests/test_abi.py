@@ -189,3 +189,15 @@ def test_nn_argument_checks(lib):
     assert planes(32, 4096, 32) == rdc.RDC_E_INVAL    # pitch < w
     assert planes(64, 100, 32) == rdc.RDC_E_INVAL     # images overlap
     assert planes(64, 256, 256) == rdc.RDC_E_INVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for more exits with a message (and
+    without touching a GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "4"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode != 0
+    assert "one GPU" in (p.stdout + p.stderr)
