@@ -51,3 +51,29 @@ def test_tune_batch(tmp_path, monkeypatch):
     assert (rec["T"], rec["rows"]) in {(4, 48), (4, 56), (8, 48), (8, 56)}
     assert b.autotune(Ts=(4, 8), rows=(48, 56), launches=4)["cached"]
     b.close()
+
+
+def test_tune_fp64_sim_keys_by_precision_and_stays_bitwise(tmp_path, monkeypatch):
+    """An FP64 grid is timed with FP64 kernels under its own cache key, and the
+    tuned launch shape still gives the oracle's bits (the one-step FP64 run)."""
+    monkeypatch.setenv("RDC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    u, v, phi = inputs.random_state(520, 300, seed=6, umax=0.02, vmax=0.02)
+    s = rdc.Sim(520, 300, inputs.PARAMS_WORKLOAD, "fp64")
+    s.set_phi(phi)
+    s.write(u, v)
+    rec = s.autotune(Ts=(4, 8), rows=(48, 64), launches=3)
+    assert (rec["T"], rec["rows"]) in {(4, 48), (4, 64), (8, 48), (8, 64)}
+    (key,) = json.load(open(tmp_path / "tune.json"))
+    assert key.endswith("/single_fp64/520x300")
+    s.stimulate([(260, 150, 6)])
+    s.step(45)
+    ref = rdc.Sim(520, 300, inputs.PARAMS_WORKLOAD, "fp64")
+    ref.set_phi(phi)
+    ref.write(u, v)
+    ref.set_block(1)
+    ref.stimulate([(260, 150, 6)])
+    ref.step(45)
+    a, b = s.read(), ref.read()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    s.close()
+    ref.close()
