@@ -279,7 +279,7 @@ const char *rdc_batch_last_error(const rdc_batch *b);
  * Learned coarse stepper: the kernels a 3x3-convolution U-Net needs to be
  * trained and run on the GPU next to the plain stepper (a surrogate that
  * advances (u, v, phi) by K steps; the plain forward-Euler stepper of Sec. 2
- * stays the judge and the fallback).  Activations are NHWC bfloat16 stored
+ * stays the reference check and the fallback).  Activations are NHWC bfloat16 stored
  * as 16-bit words, with a pixel stride `ld` (elements) so a layer can read
  * or write a channel slice of a concatenation buffer; weights of a layer are
  * [9][cout][cin] (tap = 3*(dy+1) + (dx+1)), bf16 for the convolution and fp32

@@ -1,7 +1,7 @@
 """Learned coarse stepper: a 3x3-convolution U-Net that advances the
 Oregonator state by K plain steps at once, trained and run on the GPU with
 the library's own kernels (rdc_nn_*), with the plain forward-Euler stepper of
-Sec. 2 (Eq. (1)) as data source, judge and fallback.
+Sec. 2 (Eq. (1)) as data source, reference check and fallback.
 
 Network (4 levels, 32-64-128-128 channels, NHWC bf16 activations, fp32
 accumulation and fp32 master weights):
@@ -574,13 +574,13 @@ class CoarseStepper:
         self.ulo = -float(params["q"])
         self.cmax_valid = euler_safe_c(params)
         self.sim = rdc.Sim(nx, ny, params, "fp32")
-        self.judge = rdc.Sim(nx, ny, params, "fp32")
+        self.verify_sim = rdc.Sim(nx, ny, params, "fp32")
         self.ref = rdc.Sim(nx, ny, params, "fp32") if track else None
-        for s in (self.sim, self.judge, self.ref):
+        for s in (self.sim, self.verify_sim, self.ref):
             if s is not None:
                 s.set_phi(phi)
         shape = self.sim.autotune()
-        for s in (self.judge, self.ref):
+        for s in (self.verify_sim, self.ref):
             if s is not None:
                 s.set_block(shape["T"])
                 s.set_tile_rows(shape["rows"])
@@ -701,18 +701,18 @@ class CoarseStepper:
         else:
             checked = self._since_check is None or self._since_check >= self.check_every - 1
             if checked:
-                self._copy_state(self.judge, self.sim)
-                self.judge.step(K)
+                self._copy_state(self.verify_sim, self.sim)
+                self.verify_sim.step(K)
                 self._network_step()
                 st["checks"] += 1
-                if (self._cells_off(self.judge, self.sim) > self.max_bad
-                        or self._invalid(self.judge) > 0):
+                if (self._cells_off(self.verify_sim, self.sim) > self.max_bad
+                        or self._invalid(self.verify_sim) > 0):
                     st["failed_checks"] += 1
                     self._rollback_and_replay(self.now + K)
                     self._cool = self.cooldown
                     self._since_check = None
                 else:
-                    self._copy_state(self.sim, self.judge)
+                    self._copy_state(self.sim, self.verify_sim)
                     self._since_check = 0
                 st["plain_steps"] += K
                 self.now += K
@@ -750,6 +750,6 @@ class CoarseStepper:
                 break
 
     def close(self):
-        for s in (self.sim, self.judge, self.ref):
+        for s in (self.sim, self.verify_sim, self.ref):
             if s is not None:
                 s.close()
