@@ -179,6 +179,12 @@ rdc_status rdc_set_timelapse(rdc_ctx *ctx, void *timelapse_dev, int64_t pitch, i
 /* Number of steps taken since rdc_create.  Errors: RDC_E_INVAL for NULL. */
 rdc_status rdc_get_step(const rdc_ctx *ctx, int64_t *step);
 
+/* Set the step counter, to resume a run from a snapshot (Sec. 3.1) taken at
+ * that step: arrival times and timelapse frames continue from it.  The state
+ * itself comes from rdc_write.  Errors: RDC_E_INVAL for NULL or a step
+ * outside 0 .. INT32_MAX - 8. */
+rdc_status rdc_set_step(rdc_ctx *ctx, int64_t step);
+
 /* Message of the last failed call on ctx ("" if none); with ctx == NULL the
  * last failure of rdc_create.  The string is owned by the library. */
 const char *rdc_last_error(const rdc_ctx *ctx);

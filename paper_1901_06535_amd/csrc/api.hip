@@ -429,6 +429,14 @@ rdc_status rdc_get_step(const rdc_ctx* c, int64_t* step) {
     return RDC_OK;
 }
 
+rdc_status rdc_set_step(rdc_ctx* c, int64_t step) {
+    if (!c) return RDC_E_INVAL;
+    if (step < 0 || step > INT32_MAX - 8)
+        return fail(c, RDC_E_INVAL, "step must be in 0 .. INT32_MAX - 8 (the arrival range)");
+    c->step = step;
+    return RDC_OK;
+}
+
 rdc_status rdc_copy(void* dst, const void* src, int64_t nbytes, void* hip_stream) {
     if (!dst || !src || nbytes < 0 || nbytes % 16 != 0)
         return fail(nullptr, RDC_E_INVAL, "copy needs non-NULL pointers and nbytes % 16 == 0");

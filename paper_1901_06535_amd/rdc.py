@@ -28,7 +28,7 @@ NEVER = 0x7FFFFFFF
 EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_write",
            "rdc_stimulate", "rdc_step", "rdc_read", "rdc_set_block", "rdc_set_tile_rows",
            "rdc_tile_rows_supported", "rdc_current", "rdc_set_arrival", "rdc_set_timelapse",
-           "rdc_get_step", "rdc_last_error", "rdc_copy", "rdc_status_string",
+           "rdc_get_step", "rdc_set_step", "rdc_last_error", "rdc_copy", "rdc_status_string",
            "rdc_batch_create", "rdc_batch_destroy", "rdc_batch_set_block", "rdc_batch_set_phi",
            "rdc_batch_write", "rdc_batch_stimulate", "rdc_batch_step", "rdc_batch_read",
            "rdc_batch_capture", "rdc_graph_launch", "rdc_graph_destroy", "rdc_batch_last_error",
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_set_arrival": (i32, [vp, vp, i64, ctypes.c_double]),
         "rdc_set_timelapse": (i32, [vp, vp, i64, i32]),
         "rdc_get_step": (i32, [vp, ctypes.POINTER(i64)]),
+        "rdc_set_step": (i32, [vp, i64]),
         "rdc_last_error": (ctypes.c_char_p, [vp]),
         "rdc_copy": (i32, [vp, vp, i64, vp]),
         "rdc_status_string": (ctypes.c_char_p, [i32]),
@@ -232,6 +233,10 @@ def rdc_set_arrival(ctx, ptr: Optional[int], pitch: int, theta: float) -> None:
 
 def rdc_set_timelapse(ctx, ptr: Optional[int], pitch: int, rate: int) -> None:
     _check(load().rdc_set_timelapse(ctx, ptr, pitch, rate), ctx)
+
+
+def rdc_set_step(ctx, step: int) -> None:
+    _check(load().rdc_set_step(ctx, int(step)), ctx)
 
 
 def rdc_get_step(ctx) -> int:
@@ -382,6 +387,7 @@ class Sim:
         t = self._torch
         self.arrival_plane = t.empty((self.ny, self.pitch), dtype=t.int32, device=self.device)
         rdc_set_arrival(self.ctx, self.arrival_plane.data_ptr(), self.pitch, theta)
+        self.arrival_theta = float(theta)
 
     def arrival(self) -> np.ndarray:
         self.stream.synchronize()
@@ -394,6 +400,7 @@ class Sim:
         self.timelapse_plane = t.empty((self.ny, self.pitch), dtype=self.tdtype,
                                        device=self.device)
         rdc_set_timelapse(self.ctx, self.timelapse_plane.data_ptr(), self.pitch, rate)
+        self.timelapse_rate = int(rate)
 
     def timelapse(self) -> np.ndarray:
         self.stream.synchronize()
@@ -401,6 +408,46 @@ class Sim:
 
     def synchronize(self) -> None:
         self.stream.synchronize()
+
+    # -- checkpoint / resume
+    def save_checkpoint(self, path: str, seed: Optional[int] = None) -> None:
+        """Write the state, phi, step index, parameters and any attached
+        arrival / timelapse plane to `path`.npz + `path`.json (see
+        checkpoint.py); from_checkpoint resumes bit-identically."""
+        from . import checkpoint
+        u, v = self.read()
+        arrays = {"u": u, "v": v, "phi": self.planes[4][:, : self.nx].cpu().numpy()}
+        meta = {"nx": self.nx, "ny": self.ny, "dtype": self.dtype, "params": self.params,
+                "step": self.step_index, "seed": seed}
+        if self.arrival_plane is not None:
+            arrays["arrival"] = self.arrival()
+            meta["arrival_theta"] = self.arrival_theta
+        if getattr(self, "timelapse_plane", None) is not None:
+            arrays["timelapse"] = self.timelapse()
+            meta["timelapse_rate"] = self.timelapse_rate
+        checkpoint.write(path, arrays, meta)
+
+    @classmethod
+    def from_checkpoint(cls, path: str, device=None, stream=None) -> "Sim":
+        """A new context holding the checkpoint at `path` (digests checked)."""
+        from . import checkpoint
+        arrays, meta = checkpoint.read(path)
+        s = cls(meta["nx"], meta["ny"], meta["params"], meta["dtype"], device=device,
+                stream=stream)
+        s.set_phi(arrays["phi"])
+        s.write(arrays["u"], arrays["v"])
+        rdc_set_step(s.ctx, meta["step"])
+        t = s._torch
+        if "arrival" in arrays:
+            s.enable_arrival(meta["arrival_theta"])
+            s.stream.synchronize()
+            s.arrival_plane[:, : s.nx].copy_(t.as_tensor(arrays["arrival"]))
+        if "timelapse" in arrays:
+            s.enable_timelapse(meta["timelapse_rate"])
+            s.stream.synchronize()
+            s.timelapse_plane[:, : s.nx].copy_(t.as_tensor(arrays["timelapse"]))
+        t.cuda.synchronize(s.device)
+        return s
 
     def close(self) -> None:
         if getattr(self, "ctx", None):

@@ -114,6 +114,10 @@ static void plain_context(void) {
     }
     int64_t step = -1;
     EXPECT(rdc_get_step(c, &step) == RDC_OK && step == expect_step);
+    EXPECT(rdc_set_step(c, -1) == RDC_E_INVAL);
+    EXPECT(rdc_set_step(c, (int64_t)INT32_MAX) == RDC_E_INVAL);
+    EXPECT(rdc_set_step(c, expect_step) == RDC_OK);
+    EXPECT(rdc_set_step(NULL, 0) == RDC_E_INVAL);
     EXPECT(rdc_set_block(c, 0) == RDC_OK && rdc_set_tile_rows(c, 0) == RDC_OK);
     EXPECT(rdc_step(c, 23) == RDC_OK);
 
