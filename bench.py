@@ -91,7 +91,7 @@ def main():
                     help="surrogate: (t, t+50) training pairs of 512^2 patches")
     args = ap.parse_args()
     if args.gpus != 1:
-        sys.exit("bench.py measures one GPU: this build has no multi-GPU path "
+        sys.exit("bench.py measures one GPU: the library has no multi-GPU path "
                  "(--gpus %d requested)" % args.gpus)
     if args.workload == "batch":
         return bench_batch(args)
