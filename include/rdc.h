@@ -124,8 +124,8 @@ rdc_status rdc_stimulate(rdc_ctx *ctx, const int32_t *cx, const int32_t *cy,
 
 /* Advance the state by n >= 0 forward-Euler steps (Sec. 2; how many steps
  * pass between two renders is the simulation speed, Sec. 2).  Queued
- * asynchronously: the library launches ceil(n/T) kernels that each take up to
- * T steps on chip (T from rdc_set_block).  Errors: RDC_E_INVAL for n < 0,
+ * asynchronously: the library launches ceil(n/T) kernels of near-equal length,
+ * each taking up to T steps on chip (T from rdc_set_block).  Errors: RDC_E_INVAL for n < 0,
  * RDC_E_DEVICE if a launch fails.  Faults and the non-finite flag surface at
  * the next rdc_read. */
 rdc_status rdc_step(rdc_ctx *ctx, int64_t n);

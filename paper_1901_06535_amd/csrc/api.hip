@@ -306,8 +306,13 @@ rdc_status rdc_step(rdc_ctx* c, int64_t n) {
     const int T = c->T > 0 ? c->T : auto_block(c);
     const int rows = c->tile_rows > 0 ? c->tile_rows : rdc::tile_rows_default();
     const bool f64 = c->dtype == RDC_FP64;
+    // ceil(n / T) launches of near-equal length (n = 9, T = 8 runs 5 + 4,
+    // not 8 + 1): the launch count is the least possible, and no short
+    // remainder launch pays a whole tile load and store for one or two steps.
+    int64_t launches = (n + T - 1) / T;
     while (n > 0) {
-        const int k = n < T ? static_cast<int>(n) : T;
+        const int k = static_cast<int>((n + launches - 1) / launches);
+        --launches;
         hipError_t e;
         if (k == 1)
             e = f64 ? rdc::launch_step1(step_args<double>(c), c->stream)
