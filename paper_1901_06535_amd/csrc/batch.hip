@@ -267,24 +267,19 @@ rdc::BatchArgs batch_args(const rdc_batch* b, const rdc::Item* items, int n) {
     return a;
 }
 
-// Steps per launch for advancing n steps: T-step launches and one remainder;
-// with `even`, one launch is split so the count of launches is even.
+// Steps per launch for advancing n steps: ceil(n/T) launches of near-equal
+// length (a short remainder launch would pay a whole tile load and store for
+// a step or two); with `even`, one launch more when that count is odd, so the
+// ping-pong index ends where it started (impossible only for T = 1 and odd n).
 std::vector<int> plan_launches(int64_t n, int T, bool even) {
     std::vector<int> ks;
+    int64_t m = (n + T - 1) / T;
+    if (even && m % 2 == 1 && n >= m + 1) ++m;
     while (n > 0) {
-        const int k = n < T ? static_cast<int>(n) : T;
+        const int k = static_cast<int>((n + m - 1) / m);
         ks.push_back(k);
         n -= k;
-    }
-    if (even && ks.size() % 2 == 1) {
-        for (size_t i = ks.size(); i-- > 0;) {
-            if (ks[i] >= 2) {
-                const int a = ks[i] / 2;
-                ks[i] -= a;
-                ks.insert(ks.begin() + i, a);
-                break;
-            }
-        }
+        --m;
     }
     return ks;
 }
