@@ -140,7 +140,7 @@ def main():
         T, rows = args.T, args.rows
         tune = {}
     else:
-        rec = sim.autotune(Ts=(args.T,) if args.T else (4, 6, 8),
+        rec = sim.autotune(Ts=(args.T,) if args.T else (6, 8, 10, 12),
                            rows=(args.rows,) if args.rows else (48, 56, 64, 80),
                            launches=48, use_cache=False)
         T, rows, tune = rec["T"], rec["rows"], rec["table"]
@@ -332,7 +332,7 @@ def bench_uniform(args):
     zeros = torch.zeros((wl.ny, wl.nx), dtype=torch.float32, device="cuda")
     disks = [(s.cx, s.cy, s.r) for s in wl.stimuli]
     res = {}
-    for T, rows in ((1, 0), (8, 48), (8, 56), (8, 64)):
+    for T, rows in ((1, 0), (8, 48), (8, 56), (8, 64), (10, 64), (12, 56), (12, 64)):
         sim.set_block(T)
         if rows:
             sim.set_tile_rows(rows)

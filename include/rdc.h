@@ -137,11 +137,12 @@ rdc_status rdc_step(rdc_ctx *ctx, int64_t n);
  * non-finite value since the last rdc_write (the copy is still made). */
 rdc_status rdc_read(rdc_ctx *ctx, void *u, void *v, int64_t pitch, rdc_where where);
 
-/* Steps per launch: T in 1..8, or 0 to choose by grid size (the default:
- * 8 from 1024 x 1024 cells on, else 1).  The result does not depend on T:
+/* Steps per launch: T in 1..12 (FP32) or 1..8 (FP64), or 0 to choose by grid
+ * size (the default: 8 from 1024 x 1024 cells on, else 1).  The result does not depend on T:
  * every variant of one precision computes each cell with the same expression
  * and gives bit-identical results (FP64 ones bit-identical to a plain C
- * evaluation of Eq. (1)).  Errors: RDC_E_INVAL outside 0..8. */
+ * evaluation of Eq. (1)).  Errors: RDC_E_INVAL outside 0..12 (FP32) or 0..8
+ * (FP64). */
 rdc_status rdc_set_block(rdc_ctx *ctx, int32_t T);
 
 /* Rows of a temporal-blocking tile: 0 (auto: 56 rows) or one of the

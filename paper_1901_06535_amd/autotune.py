@@ -20,8 +20,11 @@ from typing import Dict, Iterable, Optional, Sequence, Tuple
 
 from .profile_kernels import source_hash
 
-DEFAULT_T = (4, 6, 8)
+DEFAULT_T = (4, 6, 8, 10, 12)
 DEFAULT_ROWS = (48, 56, 64, 80)
+# Most steps per launch the library's tile kernels take, per precision
+# (rdc_set_block); the batched kernels take at most 8 in either.
+MAX_T = {"fp32": 12, "fp64": 8}
 
 
 def cache_path() -> str:
@@ -99,6 +102,7 @@ def tune_sim(sim, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = DEFAULT_R
     else:
         scratch = rdc.Sim(sim.nx, sim.ny, sim.params, sim.dtype, device=sim.device,
                           stream=sim.stream)
+        Ts = [T for T in Ts if T <= MAX_T[sim.dtype]]
 
         def set_shape(T, r):
             scratch.set_block(T)
@@ -128,6 +132,7 @@ def tune_batch(batch, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = (48, 
         rec = dict(hit, cached=True)
     else:
         scratch = rdc.BatchSim(batch.specs, device=batch.device, stream=batch.stream)
+        Ts = [T for T in Ts if T <= 8]
         (T, r), table = _search(scratch.step, scratch.set_block, scratch.stream, Ts, rows,
                                 launches)
         scratch.close()

@@ -352,7 +352,10 @@ rdc_status rdc_read(rdc_ctx* c, void* u, void* v, int64_t pitch, rdc_where where
 
 rdc_status rdc_set_block(rdc_ctx* c, int32_t T) {
     if (!c) return RDC_E_INVAL;
-    if (T < 0 || T > 8) return fail(c, RDC_E_INVAL, "T must be in 0..8");
+    const int tmax = c->dtype == RDC_FP64 ? rdc::kMaxBlock64 : rdc::kMaxBlock;
+    if (T < 0 || T > tmax)
+        return fail(c, RDC_E_INVAL, c->dtype == RDC_FP64 ? "T must be in 0..8 for FP64"
+                                                         : "T must be in 0..12");
     c->T = T;
     return RDC_OK;
 }

@@ -36,7 +36,10 @@ hipError_t launch_step1(const StepArgs<float>& a, hipStream_t s);
 hipError_t launch_step1(const StepArgs<double>& a, hipStream_t s);
 
 // T forward-Euler steps per launch on LDS tiles of `rows` rows (FP32).
-// T in 2..8; `rows` one of tile_rows_supported().
+// T in 2..kMaxBlock; `rows` one of tile_rows_supported().
+// Most steps one tile launch takes: FP32 (kMaxBlock), FP64 (kMaxBlock64).
+constexpr int kMaxBlock = 12;
+constexpr int kMaxBlock64 = 8;
 hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s);
 // The same for FP64 (tiles of 128 columns, 2 cells per lane).
 hipError_t launch_stepT(const StepArgs<double>& a, int T, int rows, hipStream_t s);

@@ -269,6 +269,10 @@ hipError_t stepT_rows(const StepArgs<float>& a, int T, hipStream_t s) {
         case 6: return stepT_impl<6, R>(a, s);
         case 7: return stepT_impl<7, R>(a, s);
         case 8: return stepT_impl<8, R>(a, s);
+        case 9: return stepT_impl<9, R>(a, s);
+        case 10: return stepT_impl<10, R>(a, s);
+        case 11: return stepT_impl<11, R>(a, s);
+        case 12: return stepT_impl<12, R>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

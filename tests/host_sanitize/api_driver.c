@@ -92,7 +92,7 @@ static void plain_context(void) {
     EXPECT(memcmp(hv, rv, sizeof(float) * nx * ny) == 0);
     EXPECT(rdc_read(c, ru, rv, nx - 1, RDC_HOST) == RDC_E_INVAL);
 
-    EXPECT(rdc_set_block(c, 9) == RDC_E_INVAL);
+    EXPECT(rdc_set_block(c, 13) == RDC_E_INVAL);
     EXPECT(rdc_set_block(c, -1) == RDC_E_INVAL);
     EXPECT(rdc_set_tile_rows(c, 50) == RDC_E_INVAL);
     EXPECT(rdc_tile_rows_supported(56) == 1 && rdc_tile_rows_supported(57) == 0);
@@ -102,7 +102,7 @@ static void plain_context(void) {
     EXPECT(shim_launches() == before);
     const int rows[] = {48, 56, 64, 80};
     int64_t expect_step = 0;
-    for (int T = 1; T <= 8; ++T) {
+    for (int T = 1; T <= 12; ++T) {
         for (int r = 0; r < 4; ++r) {
             EXPECT(rdc_set_block(c, T) == RDC_OK);
             EXPECT(rdc_set_tile_rows(c, rows[r]) == RDC_OK);
@@ -177,6 +177,7 @@ static void fp64_context(void) {
     b.phi = dev(plane * 8); b.pitch = pitch;
     rdc_ctx *c = NULL;
     EXPECT(rdc_create(nx, ny, RDC_FP64, &b, NULL, &c) == RDC_OK);
+    EXPECT(rdc_set_block(c, 9) == RDC_E_INVAL);     /* FP64 tiles take at most 8 steps */
     EXPECT(rdc_set_block(c, 1) == RDC_OK);
     long before = shim_launches();
     EXPECT(rdc_step(c, 5) == RDC_OK);

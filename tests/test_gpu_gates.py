@@ -16,13 +16,13 @@ from paper_1901_06535_amd import inputs, rdc
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_arrival(wl, dtype, T=None):
+def _gpu_arrival(wl, dtype, T=None, rows=56):
     s = rdc.Sim(wl.nx, wl.ny, wl.params, dtype)
     s.set_phi(wl.phi)
     s.write(wl.u0, wl.v0)
     if T:
         s.set_block(T)
-        s.set_tile_rows(56)
+        s.set_tile_rows(rows)
     s.enable_arrival(0.5)
     s.run_schedule(wl.stimuli, wl.steps)
     arr = s.arrival()
@@ -62,6 +62,7 @@ def test_gate_on_gpu_matches_oracle(name, make, expect):
     assert _fires(ref, wl) == expect                   # the oracle's own pin
     a64 = _gpu_arrival(wl, "fp64")
     assert np.array_equal(a64, ref)
-    a32 = _gpu_arrival(wl, "fp32", T=8)
-    assert _fires(a32, wl) == expect
-    assert _within_one_cell(a32, ref)
+    for T, rows in ((8, 56), (10, 64)):
+        a32 = _gpu_arrival(wl, "fp32", T=T, rows=rows)
+        assert _fires(a32, wl) == expect, (T, rows)
+        assert _within_one_cell(a32, ref), (T, rows)

@@ -124,8 +124,8 @@ def test_every_launch_shape_is_bitwise_equal_to_one_step_kernel():
     u, v, phi, disks = _ragged_case()
     ref = _run_fp32(u, v, phi, disks, T=1, rows=0)
     assert np.isfinite(ref[0]).all()
-    for rows in (48, 64, 80):
-        for T in range(2, 9):
+    for rows in (48, 56, 64, 80):
+        for T in range(2, 13):
             print_case("T=%d rows=%d" % (T, rows))
             got = _run_fp32(u, v, phi, disks, T=T, rows=rows)
             assert np.array_equal(got[0], ref[0]), (T, rows)
@@ -306,7 +306,11 @@ def test_parameter_validation():
     p["eps"] = float("inf")
     s.set_params(p)
     with pytest.raises(rdc.RdcError):
-        s.set_block(9)
+        s.set_block(13)
+    s64 = rdc.Sim(16, 16, None, "fp64")
+    with pytest.raises(rdc.RdcError):
+        s64.set_block(9)
+    s64.close()
     with pytest.raises(rdc.RdcError):
         s.step(-1)
     s.close()
