@@ -237,7 +237,7 @@ rdc_status rdc_batch_create(int32_t count, const rdc_sim_desc *sims, const rdc_b
 /* Release the batch (not the pool).  Waits for its stream.  NULL accepted. */
 rdc_status rdc_batch_destroy(rdc_batch *b);
 
-/* Steps per launch (1..8, default 8) and tile rows (48, 56 or 64, default
+/* Steps per launch (1..12, default 8) and tile rows (48, 56 or 64, default
  * 56) of the batched kernel.  Does not change results. */
 rdc_status rdc_batch_set_block(rdc_batch *b, int32_t T, int32_t rows);
 

@@ -23,7 +23,7 @@ from .profile_kernels import source_hash
 DEFAULT_T = (4, 6, 8, 10, 12)
 DEFAULT_ROWS = (48, 56, 64, 80)
 # Most steps per launch the library's tile kernels take, per precision
-# (rdc_set_block); the batched kernels take at most 8 in either.
+# (rdc_set_block; the batched kernels are FP32).
 MAX_T = {"fp32": 12, "fp64": 8}
 
 
@@ -132,7 +132,7 @@ def tune_batch(batch, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = (48, 
         rec = dict(hit, cached=True)
     else:
         scratch = rdc.BatchSim(batch.specs, device=batch.device, stream=batch.stream)
-        Ts = [T for T in Ts if T <= 8]
+        Ts = [T for T in Ts if T <= MAX_T["fp32"]]
         (T, r), table = _search(scratch.step, scratch.set_block, scratch.stream, Ts, rows,
                                 launches)
         scratch.close()

@@ -128,6 +128,10 @@ hipError_t batch_launch_T(const BatchArgs& b, int T, hipStream_t s) {
         case 6: return batch_launch<6, R>(b, s);
         case 7: return batch_launch<7, R>(b, s);
         case 8: return batch_launch<8, R>(b, s);
+        case 9: return batch_launch<9, R>(b, s);
+        case 10: return batch_launch<10, R>(b, s);
+        case 11: return batch_launch<11, R>(b, s);
+        case 12: return batch_launch<12, R>(b, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -396,7 +400,7 @@ rdc_status rdc_batch_destroy(rdc_batch* b) {
 
 rdc_status rdc_batch_set_block(rdc_batch* b, int32_t T, int32_t rows) {
     if (!b) return RDC_E_INVAL;
-    if (T < 1 || T > 8) return bfail(b, RDC_E_INVAL, "T must be in 1..8");
+    if (T < 1 || T > rdc::kMaxBlock) return bfail(b, RDC_E_INVAL, "T must be in 1..12");
     if (rows != 48 && rows != 56 && rows != 64) return bfail(b, RDC_E_INVAL, "rows must be 48, 56 or 64");
     b->T = T;
     b->rows = rows;

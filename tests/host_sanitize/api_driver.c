@@ -243,7 +243,8 @@ static void batch(void) {
     int32_t sim[2] = {0, 2}, cx[2] = {5, 63}, cy[2] = {5, 0}, r[2] = {4, 3}, bad_sim = 7;
     EXPECT(rdc_batch_stimulate(bt, sim, cx, cy, r, 2) == RDC_OK);
     EXPECT(rdc_batch_stimulate(bt, &bad_sim, cx, cy, r, 1) == RDC_E_INVAL);
-    EXPECT(rdc_batch_set_block(bt, 9, 56) == RDC_E_INVAL);
+    EXPECT(rdc_batch_set_block(bt, 13, 56) == RDC_E_INVAL);
+    EXPECT(rdc_batch_set_block(bt, 12, 48) == RDC_OK);
     EXPECT(rdc_batch_set_block(bt, 6, 48) == RDC_OK);
     EXPECT(rdc_batch_step(bt, 20) == RDC_OK);
     EXPECT(rdc_batch_step(bt, -1) == RDC_E_INVAL);

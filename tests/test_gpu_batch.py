@@ -51,7 +51,7 @@ def _single(spec, state, disk, T, nsteps):
     return out
 
 
-@pytest.mark.parametrize("T,rows", [(8, 56), (5, 48), (8, 64), (1, 56)])
+@pytest.mark.parametrize("T,rows", [(8, 56), (5, 48), (8, 64), (1, 56), (12, 48), (10, 64)])
 def test_batch_equals_single_grids_bitwise(T, rows):
     specs, states, disks = _case()
     b = _batch(specs, states, disks, T, rows)
