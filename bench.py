@@ -140,7 +140,7 @@ def main():
         T, rows = args.T, args.rows
         tune = {}
     else:
-        rec = sim.autotune(Ts=(args.T,) if args.T else (6, 8, 10, 12),
+        rec = sim.autotune(Ts=(args.T,) if args.T else (6, 8, 9, 10, 11, 12),
                            rows=(args.rows,) if args.rows else (48, 56, 64, 80),
                            launches=48, use_cache=False)
         T, rows, tune = rec["T"], rec["rows"], rec["table"]

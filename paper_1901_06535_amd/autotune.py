@@ -20,7 +20,7 @@ from typing import Dict, Iterable, Optional, Sequence, Tuple
 
 from .profile_kernels import source_hash
 
-DEFAULT_T = (4, 6, 8, 10, 12)
+DEFAULT_T = (4, 6, 8, 9, 10, 11, 12)
 DEFAULT_ROWS = (48, 56, 64, 80)
 # Most steps per launch the library's tile kernels take, per precision
 # (rdc_set_block; the batched kernels are FP32).

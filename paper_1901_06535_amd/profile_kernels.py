@@ -138,7 +138,7 @@ def summarize(fetch_csv: str, write_csv: str, out_json: str) -> None:
     with open(out_json, "w") as fh:
         json.dump(rec, fh, indent=1)
 
-CANDIDATES = [(T, r) for T in (4, 6, 8, 10, 12) for r in (48, 56, 64, 80)]
+CANDIDATES = [(T, r) for T in (4, 6, 8, 9, 10, 11, 12) for r in (48, 56, 64, 80)]
 CANDIDATES64 = [(8, 56), (8, 64)]
 LAUNCHES = 4
 

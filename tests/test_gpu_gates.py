@@ -62,7 +62,7 @@ def test_gate_on_gpu_matches_oracle(name, make, expect):
     assert _fires(ref, wl) == expect                   # the oracle's own pin
     a64 = _gpu_arrival(wl, "fp64")
     assert np.array_equal(a64, ref)
-    for T, rows in ((8, 56), (10, 64)):
+    for T, rows in ((8, 56), (10, 64), (11, 64)):
         a32 = _gpu_arrival(wl, "fp32", T=T, rows=rows)
         assert _fires(a32, wl) == expect, (T, rows)
         assert _within_one_cell(a32, ref), (T, rows)
