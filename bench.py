@@ -332,7 +332,7 @@ def bench_uniform(args):
     zeros = torch.zeros((wl.ny, wl.nx), dtype=torch.float32, device="cuda")
     disks = [(s.cx, s.cy, s.r) for s in wl.stimuli]
     res = {}
-    for T, rows in ((1, 0), (8, 48), (8, 56), (8, 64), (10, 64), (12, 56), (12, 64)):
+    for T, rows in ((1, 0), (8, 48), (8, 56), (8, 64), (10, 64), (11, 64), (12, 56), (12, 64)):
         sim.set_block(T)
         if rows:
             sim.set_tile_rows(rows)
