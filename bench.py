@@ -1,24 +1,30 @@
-"""Throughput of the MI355X Oregonator stepper on the circuit workload.
+"""Throughput of the MI355X Oregonator stepper.
 
-One benchmark step = one whole run of the workload: a 4096x4096 FP32 grid with
-a seeded circuit phi map (16-wide excitable channels at phi=0.054 on an
-inhibitory phi=0.2 background, with diode gaps and AND T-junctions), u = v = 0
-at the start, 256 r=5 stimulus disks applied at seeded steps, and 10,000
-forward-Euler steps of Eq. (1) with T steps per launch.  Inputs are resident
-in HBM before the timed region; the state is reset on the device at the start
-of every run.
+Default workload (the scale case): a 16384x16384 FP32 grid with phi ~ U[0.04,
+0.08) i.i.d. per cell, u = v = 0 with 64 r=5 stimulus disks at t=0, and 2,000
+forward-Euler steps of Eq. (1) with T steps per launch.  One benchmark step =
+one whole run of the workload.  Inputs are resident in HBM before the timed
+region; the state is reset on the device at the start of every run.
 
 Prints one JSON line: GCell-updates/s (whole job), the roofline of the
-dominant kernel (measured with HIP events on the stream it runs on) and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+dominant kernel (its average launch measured with HIP events on the stream it
+runs on), the one-step kernel's HBM rate beside a plain copy kernel and the
+runtime's device-to-device copy, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+    python bench.py --workload circuit     # 4096^2 circuit map, 10,000 steps
+    python bench.py --workload batch       # 512-grid sweep, 5,000 steps
+    python bench.py --workload surrogate   # learned coarse stepper on 2048^2
+    python bench.py --workload variants    # 16384^2: every launch shape, FP32 and FP64
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -49,44 +55,99 @@ def load_traffic(key: str):
     return ent
 
 
-def cpu_baseline(wl, target_s: float = 12.0):
-    """The FP64 oracle on the first steps of the same workload, all host
-    cores, ~target_s seconds of work."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, target_s: float = 24.0, runs: int = 3):
+    """The FP64 oracle on the same workload, all host cores: `runs` timed
+    samples of the same number of steps from the workload's start (stimuli
+    at step 0 applied), about target_s seconds in all; the median rate."""
     import oracle
-    cores = os.cpu_count() or 1
-    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
     run = oracle.Run(wl.u0, wl.v0, wl.phi, wl.params)
-    first = [s for s in wl.stimuli if s.step == 0]
-    run.stimulate([(s.cx, s.cy, s.r) for s in first])
+    run.stimulate([(s.cx, s.cy, s.r) for s in wl.stimuli if s.step == 0])
     t0 = time.perf_counter()
-    run.advance(2)
+    run.advance(1)
     probe = time.perf_counter() - t0
-    n = max(2, int(target_s / max(probe / 2, 1e-6)))
-    t0 = time.perf_counter()
-    run.advance(n)
-    dt = time.perf_counter() - t0
-    return {"value": wl.nx * wl.ny * n / dt / 1e9, "unit": "GCell-updates/s",
-            "cores": int(os.environ.get("OMP_NUM_THREADS", cores)), "kind": "oracle",
-            "sample": "FP64 oracle, first %d of %d steps of the same %dx%d circuit workload "
-                      "(%.1f s)" % (n, wl.steps, wl.nx, wl.ny, dt)}
+    n = max(1, int(target_s / runs / max(probe, 1e-6)))
+    rates = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        run.advance(n)
+        rates.append(wl.nx * wl.ny * n / (time.perf_counter() - t0) / 1e9)
+    del run
+    return {"value": round(statistics.median(rates), 4), "unit": "GCell-updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": "FP64 oracle (C, OpenMP over rows) on the same %dx%d workload: median of "
+                      "%d runs of %d steps each from its start (%s)"
+                      % (wl.nx, wl.ny, runs, n, ", ".join("%.3f" % r for r in rates)),
+            "cpu": cpu_model(), "nproc": os.cpu_count()}
+
+
+def _hip_memcpy_d2d():
+    """hipMemcpyAsync of the HIP runtime (device to device), for the
+    bandwidth ceiling next to the library's own copy kernel."""
+    lib = ctypes.CDLL("libamdhip64.so")
+    fn = lib.hipMemcpyAsync
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                   ctypes.c_void_p]
+    return fn
+
+
+def copy_ceilings(stream, nbytes: int = 2 << 30, reps: int = 10):
+    """Read+write GB/s of the library's copy kernel and of hipMemcpyAsync
+    (device to device) on `nbytes` buffers, HIP events on `stream`."""
+    import torch
+    from paper_1901_06535_amd import rdc
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    memcpy = _hip_memcpy_d2d()
+    out = {}
+    for name in ("copy_kernel", "hipMemcpyAsync_d2d"):
+        def go():
+            if name == "copy_kernel":
+                rdc.rdc_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream)
+            else:
+                rc = memcpy(dst.data_ptr(), src.data_ptr(), nbytes, 3, stream.cuda_stream)
+                if rc != 0:
+                    raise RuntimeError("hipMemcpyAsync failed: %d" % rc)
+        go()
+        e0, e1 = _events()
+        e0.record(stream)
+        for _ in range(reps):
+            go()
+        e1.record(stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / reps
+        out[name + "_GBs"] = round(2 * nbytes / t / 1e9, 1)
+    del src, dst
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--run-steps", type=int, default=10000)
     ap.add_argument("--T", type=int, default=0, help="steps per launch (0 = autotune)")
     ap.add_argument("--rows", type=int, default=0, help="tile rows (0 = autotune)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--workload", default="circuit",
-                    choices=("circuit", "batch", "uniform", "surrogate"),
-                    help="circuit: 4096^2 circuit map, 10,000 steps (default); batch: 512-grid "
-                         "sweep, 5,000 steps, batched vs per-grid; uniform: 16384^2, 2,000 steps; "
-                         "surrogate: learned coarse stepper trained on 512^2 patches, run on a "
-                         "2048^2 circuit for 50,000 steps against the plain stepper")
+    ap.add_argument("--workload", default="uniform",
+                    choices=("uniform", "circuit", "batch", "surrogate", "variants"),
+                    help="uniform: 16384^2, phi ~ U[0.04, 0.08), 64 disks, 2,000 steps "
+                         "(default); circuit: 4096^2 circuit map, 256 disks, 10,000 steps; "
+                         "batch: 512-grid sweep, 5,000 steps, batched vs per-grid; surrogate: "
+                         "learned coarse stepper trained on 512^2 patches, run on a 2048^2 "
+                         "circuit for 50,000 steps against the plain stepper; variants: every "
+                         "launch shape on the 16384^2 grid, FP32 and FP64")
     ap.add_argument("--train-pairs", type=int, default=20000,
                     help="surrogate: (t, t+50) training pairs of 512^2 patches")
     args = ap.parse_args()
@@ -95,18 +156,28 @@ def main():
                  "(--gpus %d requested)" % args.gpus)
     if args.workload == "batch":
         return bench_batch(args)
-    if args.workload == "uniform":
-        return bench_uniform(args)
+    if args.workload == "variants":
+        return bench_variants(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    return bench_plain(args)
 
+
+def bench_plain(args):
+    """The plain stepper on one grid: the uniform 16384^2 workload (default)
+    or the 4096^2 circuit workload."""
     import torch
     from paper_1901_06535_amd import inputs, rdc
 
     if not os.path.exists(rdc.LIB_PATH):
         from paper_1901_06535_amd import build
         build.build()
-    wl = inputs.circuit(n=args.n, seed=1002, steps=args.run_steps, ndisks=256)
+    if args.workload == "circuit":
+        wl = inputs.circuit(n=4096, seed=1002, steps=10000, ndisks=256)
+        label = "circuit_%dx%d_%dsteps" % (wl.nx, wl.ny, wl.steps)
+    else:
+        wl = inputs.uniform_random_phi(n=16384, seed=1003, steps=2000, ndisks=64)
+        label = "uniform_phi_%dx%d_%dsteps" % (wl.nx, wl.ny, wl.steps)
     sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
     sim.set_phi(wl.phi)
     dev = torch.device("cuda")
@@ -123,13 +194,13 @@ def main():
         sched = [(s.step + start, s.cx, s.cy, s.r) for s in wl.stimuli]
         sim.run_schedule(sched, start + wl.steps)
 
-    # -- pick steps per launch and tile height by timing this grid's shape
     def time_steps(T, rows, n):
         sim.set_block(T)
-        sim.set_tile_rows(rows)
+        if rows:
+            sim.set_tile_rows(rows)
         reset()
         sim.step(2 * T)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1 = _events()
         e0.record(stream)
         sim.step(n)
         e1.record(stream)
@@ -142,7 +213,7 @@ def main():
     else:
         rec = sim.autotune(Ts=(args.T,) if args.T else (6, 8, 9, 10, 11, 12),
                            rows=(args.rows,) if args.rows else (48, 56, 64, 80),
-                           launches=48, use_cache=False)
+                           launches=24 if wl.nx > 8192 else 48, use_cache=False)
         T, rows, tune = rec["T"], rec["rows"], rec["table"]
     sim.set_block(T)
     sim.set_tile_rows(rows)
@@ -150,7 +221,7 @@ def main():
     for _ in range(args.warmup):
         one_run()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = _events()
     t_wall = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
@@ -159,13 +230,13 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     t = e0.elapsed_time(e1) / 1e3
-    updates = wl.nx * wl.ny * wl.steps * args.steps
+    cells = wl.nx * wl.ny
+    updates = cells * wl.steps * args.steps
     value = updates / t / 1e9
 
     # -- dominant kernel: average launch of the T-step kernel, HIP events on its stream
-    nlaunch = 200
+    nlaunch = 40 if cells > (1 << 26) else 200
     t_k = time_steps(T, rows, T * nlaunch) / nlaunch
-    cells = wl.nx * wl.ny
     flops = FLOP_PER_UPDATE * cells * T
     achieved_tf = flops / t_k / 1e12
     achieved_bw = BYTES_PER_CELL_LAUNCH * cells / t_k / 1e9
@@ -177,16 +248,26 @@ def main():
     hbm_eff = {"bound": "hbm", "achieved": round(achieved_bw, 1), "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "frac": round(achieved_bw / HBM_PEAK_GBS, 4),
                "traffic": traf["bytes_per_launch"] if traf else None}
+    # The binding roof is the one whose attainable rate is lower, i.e. the
+    # one the kernel reaches the larger fraction of.
     roof = alu if alu["frac"] >= hbm_eff["frac"] else hbm_eff
     other = hbm_eff if roof is alu else alu
+
+    # -- the one-step kernel (20 B per cell-update) against the copy ceilings
+    n1 = 20 if cells > (1 << 26) else 200
+    t1 = time_steps(1, 0, n1) / n1
+    one_step = {"kernel": "k_step1<float>", "launch_ms": round(1e3 * t1, 4),
+                "achieved_GBs": round(BYTES_PER_CELL_LAUNCH * cells / t1 / 1e9, 1),
+                "gcells": round(cells / t1 / 1e9, 1)}
+    one_step["frac_of_peak"] = round(one_step["achieved_GBs"] / HBM_PEAK_GBS, 4)
+    one_step.update(copy_ceilings(stream))
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GCell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "circuit_%dx%d_%dsteps" % (wl.nx, wl.ny, wl.steps),
-                   "grid": [wl.nx, wl.ny], "steps_per_run": wl.steps,
+        "config": {"workload": label, "grid": [wl.nx, wl.ny], "steps_per_run": wl.steps,
                    "stimuli": len(wl.stimuli), "steps_per_launch": T, "tile_rows": rows,
                    "parallelism": "single GPU"},
         "roofline": dict(roof, kernel="k_stepT<T=%d,rows=%d>" % (T, rows),
@@ -195,13 +276,16 @@ def main():
                          algorithmic="%d FLOP/update x %d updates; %d B/cell x %d cells"
                                      % (FLOP_PER_UPDATE, cells * T, BYTES_PER_CELL_LAUNCH, cells)),
         "roofline_other": other,
+        "one_step_kernel": one_step,
         "tuning_us_per_step": tune,
         "wall_s": round(wall, 3),
     }
+    sim.close()
+    del u0, v0
+    torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
-    sim.close()
 
 
 def _events():
@@ -317,9 +401,9 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_uniform(args):
-    """16384^2, phi ~ U[0.04, 0.08), 64 disks, 2,000 steps: the one-step
-    streaming kernel (HBM roofline) and the autotuned T-step kernel."""
+def bench_variants(args):
+    """16384^2, phi ~ U[0.04, 0.08), 64 disks, 2,000 steps: every launch
+    shape of the FP32 kernels, and the FP64 kernels on the same inputs."""
     import torch
     from paper_1901_06535_amd import inputs, rdc
 
@@ -375,7 +459,7 @@ def bench_uniform(args):
         "metric": METRIC, "value": round(res[best], 2), "unit": "GCell-updates/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "uniform_phi_16384x16384_2000steps", "best": best},
+        "config": {"workload": "uniform_phi_16384x16384_2000steps_variants", "best": best},
         "per_variant_gcells": {k: round(v, 1) for k, v in res.items()},
         "one_step_kernel_hbm": {"achieved_GBs": round(t1 * BYTES_PER_CELL_LAUNCH, 1),
                                 "peak_GBs": HBM_PEAK_GBS,

@@ -31,8 +31,8 @@
  *     hipStream_t passed as void*; NULL = the legacy default stream).  Calls
  *     that take HOST pointers copy synchronously and have finished with the
  *     pointer when they return; calls on DEVICE pointers are asynchronous on
- *     that stream.  rdc_read is the only call that always waits for the
- *     stream; it reports device errors and the non-finite flag.
+ *     that stream.  rdc_read and rdc_current always wait for the stream;
+ *     they report device errors and the non-finite flag.
  *   - A context is not thread-safe.  Distinct contexts are independent.
  */
 #ifndef RDC_H
@@ -108,7 +108,8 @@ rdc_status rdc_set_phi(rdc_ctx *ctx, const void *phi, int64_t pitch, rdc_where w
 
 /* Replace the state (u, v) by the given planes (ctx dtype, `pitch` elements
  * per row), reset the non-finite flag, keep the step counter.  Used for
- * initial conditions and to resume from rdc_read output.
+ * initial conditions (the medium's state before stimulation, Sec. 2) and to
+ * resume from a snapshot (Sec. 3.1) taken by rdc_read.
  * Errors: RDC_E_INVAL for NULL or pitch < nx. */
 rdc_status rdc_write(rdc_ctx *ctx, const void *u, const void *v, int64_t pitch,
                      rdc_where where);
@@ -127,7 +128,7 @@ rdc_status rdc_stimulate(rdc_ctx *ctx, const int32_t *cx, const int32_t *cy,
  * asynchronously: the library launches ceil(n/T) kernels of near-equal length,
  * each taking up to T steps on chip (T from rdc_set_block).  Errors: RDC_E_INVAL for n < 0,
  * RDC_E_DEVICE if a launch fails.  Faults and the non-finite flag surface at
- * the next rdc_read. */
+ * the next rdc_read or rdc_current. */
 rdc_status rdc_step(rdc_ctx *ctx, int64_t n);
 
 /* Snapshot (Sec. 3.1): wait for the stream, then copy the current u and v
@@ -138,7 +139,9 @@ rdc_status rdc_step(rdc_ctx *ctx, int64_t n);
 rdc_status rdc_read(rdc_ctx *ctx, void *u, void *v, int64_t pitch, rdc_where where);
 
 /* Steps per launch: T in 1..12 (FP32) or 1..8 (FP64), or 0 to choose by grid
- * size (the default: 8 from 1024 x 1024 cells on, else 1).  The result does not depend on T:
+ * size (the default: 8 from 1024 x 1024 cells on, else 1).  A launch runs T
+ * steps on chip between two visits to memory, as the app runs several steps
+ * between two rendered frames (Sec. 2).  The result does not depend on T:
  * every variant of one precision computes each cell with the same expression
  * and gives bit-identical results (FP64 ones bit-identical to a plain C
  * evaluation of Eq. (1)).  Errors: RDC_E_INVAL outside 0..12 (FP32) or 0..8
@@ -153,9 +156,13 @@ rdc_status rdc_set_tile_rows(rdc_ctx *ctx, int32_t rows);
 /* Non-zero if `rows` is a tile height rdc_set_tile_rows accepts. */
 int32_t rdc_tile_rows_supported(int32_t rows);
 
-/* Device addresses of the planes that hold the current u and v (zero-copy
- * view; valid until the next rdc_step or rdc_write).  Does not wait.
- * Errors: RDC_E_INVAL for NULL outputs. */
+/* Device addresses of the planes that hold the current u and v: a zero-copy
+ * view of the state at a step boundary, the device-side form of the
+ * snapshot of Sec. 3.1 (valid until the next rdc_step or rdc_write).  Like
+ * rdc_read it waits for the stream and reports what the queued work left:
+ * RDC_E_DEVICE for a device error, RDC_E_NONFINITE if any step produced a
+ * non-finite value since the last rdc_write; the addresses are stored in
+ * both cases.  Errors: RDC_E_INVAL for NULL outputs. */
 rdc_status rdc_current(rdc_ctx *ctx, void **u_dev, void **v_dev);
 
 /* Attach (or, with NULL, detach) a caller-owned int32 device plane that
@@ -267,7 +274,9 @@ rdc_status rdc_batch_read(rdc_batch *b, int32_t sim, void *u, void *v, int64_t p
  * running them; rdc_graph_launch then replays all of them as one submission
  * on the batch's stream and advances the batch by n steps each time.  The
  * recording always holds an even number of launches (one launch is split if
- * needed), so replays keep the ping-pong planes consistent; n must be >= 2.
+ * needed) and is made once from each ping-pong copy of the planes; a replay
+ * runs the one that starts from the copy holding the current state, so
+ * eager rdc_batch_step calls may come between replays; n must be >= 2.
  * The graph refers to the batch, which must outlive it.  Errors:
  * RDC_E_INVAL for n < 2 or NULL; RDC_E_DEVICE if capture fails. */
 rdc_status rdc_batch_capture(rdc_batch *b, int64_t n, rdc_graph **out);

@@ -68,6 +68,8 @@ def _load():
                                  i32p, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8),
                                  i64, ctypes.POINTER(ctypes.c_int64)]
         lib.rdco_run.restype = ctypes.c_int
+        lib.rdco_threads.argtypes = []
+        lib.rdco_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -94,6 +96,11 @@ def step(u, v, phi, params) -> Tuple[np.ndarray, np.ndarray]:
     lib.rdco_step(nx, ny, ctypes.byref(p), _ptr(u, ctypes.c_double), _ptr(v, ctypes.c_double),
                   _ptr(phi, ctypes.c_double), _ptr(un, ctypes.c_double), _ptr(vn, ctypes.c_double))
     return un, vn
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP loops run on."""
+    return int(_load().rdco_threads())
 
 
 def euler_factor(params, u: float, v: float, phi: float) -> float:

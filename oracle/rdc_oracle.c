@@ -39,12 +39,24 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     double eps, f, q, D_u, dt, dx;
 } rdco_params;
 
 #define RDCO_NEVER INT32_MAX
+
+/* Threads the OpenMP loops below run on (1 in a serial build). */
+int rdco_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Value of u at (x, y), or of the edge cell (xc, yc) when (x, y) is outside
  * the grid: the zero-flux ghost of the cell-centred grid. */

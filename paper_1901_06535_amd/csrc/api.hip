@@ -144,6 +144,18 @@ rdc_status copy_plane(rdc_ctx* c, void* dst, int64_t dpitch, const void* src, in
     return RDC_OK;
 }
 
+// Wait for the context's stream; report a device error, else the sticky
+// non-finite flag (the checks rdc_read and rdc_current make).
+rdc_status sync_and_check(rdc_ctx* c, const char* what) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, what);
+    int flag = 0;
+    e = hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "flag read");
+    if (flag) return fail(c, RDC_E_NONFINITE, "a non-finite u or v was produced");
+    return RDC_OK;
+}
+
 int auto_block(const rdc_ctx* c) {
     // Several steps per launch once the grid is large enough to fill the
     // chip with tiles; one step per launch for small grids.
@@ -332,11 +344,8 @@ rdc_status rdc_read(rdc_ctx* c, void* u, void* v, int64_t pitch, rdc_where where
     if (!c) return RDC_E_INVAL;
     if ((u || v) && pitch < c->nx) return fail(c, RDC_E_INVAL, "pitch < nx");
     DeviceGuard g(c->device);
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "device error before read");
-    int flag = 0;
-    e = hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(c, e, "flag read");
+    const rdc_status st = sync_and_check(c, "device error before read");
+    if (st != RDC_OK && st != RDC_E_NONFINITE) return st;
     const hipMemcpyKind kind = where == RDC_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (u) {
         rdc_status s = copy_plane(c, u, pitch, c->u[c->cur], c->pitch, kind, true);
@@ -346,8 +355,7 @@ rdc_status rdc_read(rdc_ctx* c, void* u, void* v, int64_t pitch, rdc_where where
         rdc_status s = copy_plane(c, v, pitch, c->v[c->cur], c->pitch, kind, true);
         if (s != RDC_OK) return s;
     }
-    if (flag) return fail(c, RDC_E_NONFINITE, "a non-finite u or v was produced");
-    return RDC_OK;
+    return st;
 }
 
 rdc_status rdc_set_block(rdc_ctx* c, int32_t T) {
@@ -370,12 +378,14 @@ rdc_status rdc_set_tile_rows(rdc_ctx* c, int32_t rows) {
     return RDC_OK;
 }
 
+
 rdc_status rdc_current(rdc_ctx* c, void** u_dev, void** v_dev) {
     if (!c) return RDC_E_INVAL;
     if (!u_dev || !v_dev) return fail(c, RDC_E_INVAL, "NULL output");
     *u_dev = c->u[c->cur];
     *v_dev = c->v[c->cur];
-    return RDC_OK;
+    DeviceGuard g(c->device);
+    return sync_and_check(c, "device error before current");
 }
 
 rdc_status rdc_set_arrival(rdc_ctx* c, int32_t* arrival, int64_t pitch, double theta) {

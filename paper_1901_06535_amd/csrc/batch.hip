@@ -164,10 +164,13 @@ struct rdc_batch {
     std::string err;
 };
 
+// One recording of the launch sequence per ping-pong parity: entry p starts
+// from the planes with index p, so a replay is right whichever planes hold
+// the state when it is launched (eager steps between replays may flip it).
 struct rdc_graph {
     rdc_batch* b = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     int64_t n = 0;
 };
 
@@ -532,21 +535,26 @@ rdc_status rdc_batch_capture(rdc_batch* b, int64_t n, rdc_graph** out) {
         return bfail(b, RDC_E_NOMEM, "host allocation failed");
     }
     const int cur0 = b->cur;
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     rdc_status s = RDC_OK;
-    if (e == hipSuccess) s = run_launches(b, ks, cs);
-    hipGraph_t graph = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
-    b->cur = cur0;  // an even number of launches leaves the ping-pong index unchanged
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess && s == RDC_OK) e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
+    for (int p = 0; p < 2 && e == hipSuccess && s == RDC_OK; ++p) {
+        b->cur = p;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) s = run_launches(b, ks, cs);
+        const hipError_t e2 = hipStreamEndCapture(cs, &gr->graph[p]);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess && s == RDC_OK)
+            e = hipGraphInstantiate(&gr->exec[p], gr->graph[p], nullptr, nullptr, 0);
+    }
+    b->cur = cur0;  // capture queues nothing: the state is where it was
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess || s != RDC_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
+        for (int p = 0; p < 2; ++p) {
+            if (gr->exec[p]) (void)hipGraphExecDestroy(gr->exec[p]);
+            if (gr->graph[p]) (void)hipGraphDestroy(gr->graph[p]);
+        }
         delete gr;
         return s != RDC_OK ? s : bhip(b, e, "graph capture");
     }
-    gr->graph = graph;
     gr->b = b;
     gr->n = n;
     *out = gr;
@@ -556,8 +564,9 @@ rdc_status rdc_batch_capture(rdc_batch* b, int64_t n, rdc_graph** out) {
 rdc_status rdc_graph_launch(rdc_graph* g) {
     if (!g || !g->b) return RDC_E_INVAL;
     Dev d(g->b->device);
-    hipError_t e = hipGraphLaunch(g->exec, g->b->stream);
+    hipError_t e = hipGraphLaunch(g->exec[g->b->cur], g->b->stream);
     if (e != hipSuccess) return bhip(g->b, e, "graph launch");
+    // an even number of launches: the state ends in the planes it started in
     g->b->step += g->n;
     return RDC_OK;
 }
@@ -568,8 +577,10 @@ rdc_status rdc_graph_destroy(rdc_graph* g) {
         Dev d(g->b->device);
         (void)hipStreamSynchronize(g->b->stream);
     }
-    if (g->exec) (void)hipGraphExecDestroy(g->exec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (int p = 0; p < 2; ++p) {
+        if (g->exec[p]) (void)hipGraphExecDestroy(g->exec[p]);
+        if (g->graph[p]) (void)hipGraphDestroy(g->graph[p]);
+    }
     delete g;
     return RDC_OK;
 }

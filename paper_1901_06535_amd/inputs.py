@@ -208,6 +208,39 @@ def _draw_diode_gap(blk: np.ndarray, row0: int, xl: int, gap: int, tip: int,
                 blk[i, xl + gap + k] = _CH
 
 
+def spacing_ok(t: int, x: int, y: int, tj: int, xj: int, yj: int) -> bool:
+    """Whether two input disks (step t, centre (x, y)) and (tj, (xj, yj))
+    keep the space-time spacing: the later one lands where no wave of the
+    earlier one can be yet, |x - x_j| >= FRONT_SPEED_BOUND * |t - t_j| +
+    DISK_MARGIN (Euclidean distance bounds the path along the channels from
+    below)."""
+    return bool(np.hypot(x - xj, y - yj) >= FRONT_SPEED_BOUND * abs(t - tj) + DISK_MARGIN)
+
+
+def _spaced_disks(rng: np.random.Generator, active: np.ndarray, steps: int,
+                  ndisks: int) -> List[Stimulus]:
+    """Up to ``ndisks`` r=5 input disks wholly inside the ``active`` cells at
+    steps drawn uniformly from [0, steps): candidates (step, centre) are
+    drawn independently and taken in the order drawn, each kept if it keeps
+    the space-time spacing (``spacing_ok``) with every disk kept so far,
+    earlier or later in time; the kept disks are returned in time order.
+    (Catalysing medium that an earlier wave has left refractory drives
+    forward Euler at dt = 0.001 into divergence.)"""
+    fits = _disk_fits(active, STIM_RADIUS)
+    fy, fx = np.nonzero(fits)
+    cand_t = rng.integers(0, steps, size=8 * ndisks)
+    cand_p = rng.integers(0, fy.size, size=8 * ndisks)
+    kept = []
+    for t, p in zip(cand_t, cand_p):
+        t, y, x = int(t), int(fy[p]), int(fx[p])
+        if all(spacing_ok(t, x, y, tj, xj, yj) for (tj, yj, xj) in kept):
+            kept.append((t, y, x))
+            if len(kept) == ndisks:
+                break
+    kept.sort()
+    return [Stimulus(t, x, y, STIM_RADIUS) for t, y, x in kept]
+
+
 def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 256,
             tile: int = 256, and_phi_gap: float = AND_PHI_GAP) -> Workload:
     """Seeded circuit phi map: excitable 16-wide channels (0.054) on an
@@ -217,7 +250,7 @@ def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 2
     channels of neighbouring tiles join.  Up to ``ndisks`` r=5 input disks lie
     wholly inside excitable channels at uniformly random steps in [0, steps),
     spaced so that no disk lands where an earlier disk's wave can already
-    have passed (see below).  (Catalysing the phi=0.2 background, or
+    have passed (``_spaced_disks``).  (Catalysing the phi=0.2 background, or
     re-exciting medium still refractory from an earlier wave, drives forward
     Euler at dt=0.001 into divergence.)"""
     if n % tile:
@@ -234,30 +267,7 @@ def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 2
     lut = np.array([PHI_INHIBITORY, PHI_EXCITABLE, DIODE_PHI_GAP, and_phi_gap],
                    dtype=np.float32)
     phi = lut[lab]
-    # Input disks wholly inside excitable channels, placed in time order: a
-    # candidate (step t, centre x) is kept only if no earlier disk (t_j, x_j)
-    # could have sent a wave there yet, i.e. |x - x_j| >= FRONT_SPEED_BOUND *
-    # (t - t_j) + DISK_MARGIN (Euclidean distance bounds the path along the
-    # channels from below).  Catalysing medium that an earlier wave has left
-    # refractory drives forward Euler at dt = 0.001 into divergence.
-    fits = _disk_fits(lab == _CH, STIM_RADIUS)
-    fy, fx = np.nonzero(fits)
-    cand_t = rng.integers(0, steps, size=8 * ndisks)
-    cand_p = rng.integers(0, fy.size, size=8 * ndisks)
-    order = np.argsort(cand_t, kind="stable")
-    kept = []
-    for c in order:
-        t, y, x = int(cand_t[c]), int(fy[cand_p[c]]), int(fx[cand_p[c]])
-        ok = True
-        for (tj, yj, xj) in kept:
-            if np.hypot(x - xj, y - yj) < FRONT_SPEED_BOUND * (t - tj) + DISK_MARGIN:
-                ok = False
-                break
-        if ok:
-            kept.append((t, y, x))
-            if len(kept) == ndisks:
-                break
-    stim = [Stimulus(t, x, y, STIM_RADIUS) for t, y, x in kept]
+    stim = _spaced_disks(rng, lab == _CH, steps, ndisks)
     wl = Workload("circuit_%d" % n, n, n, dict(PARAMS_WORKLOAD), phi,
                   _zeros(n, n), _zeros(n, n), stim, steps, seed)
     wl.extra["motif_counts"] = [int((motifs == i).sum()) for i in range(len(_MOTIFS))]
@@ -430,4 +440,5 @@ __all__: Sequence[str] = [
     "PHI_EXCITABLE", "PHI_INHIBITORY", "Stimulus", "Workload", "SimSpec",
     "single_disk", "uniform_random_phi", "circuit", "diode_case", "and_case",
     "batch_sweep", "random_state", "random_disks", "pitch_for", "lattice_circuit",
+    "spacing_ok",
 ]

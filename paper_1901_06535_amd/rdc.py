@@ -220,11 +220,16 @@ def rdc_tile_rows_supported(rows: int) -> bool:
     return bool(load().rdc_tile_rows_supported(rows))
 
 
-def rdc_current(ctx) -> Tuple[int, int]:
+def rdc_current(ctx) -> Tuple[int, int, int]:
+    """Returns (u address, v address, status); the status is RDC_OK or
+    RDC_E_NONFINITE (the addresses are valid in both cases); raises on other
+    errors."""
     u = ctypes.c_void_p()
     v = ctypes.c_void_p()
-    _check(load().rdc_current(ctx, ctypes.byref(u), ctypes.byref(v)), ctx)
-    return u.value, v.value
+    s = load().rdc_current(ctx, ctypes.byref(u), ctypes.byref(v))
+    if s not in (RDC_OK, RDC_E_NONFINITE):
+        _check(s, ctx)
+    return u.value, v.value, s
 
 
 def rdc_set_arrival(ctx, ptr: Optional[int], pitch: int, theta: float) -> None:
@@ -377,9 +382,14 @@ class Sim:
             raise RdcError(s, rdc_last_error(self.ctx))
         return u, v
 
-    def current(self):
-        """Torch views (ny, nx) of the planes holding the current u and v."""
-        pu, pv = rdc_current(self.ctx)
+    def current(self, allow_nonfinite: bool = False):
+        """Torch views (ny, nx) of the planes holding the current u and v.
+        Waits for the stream; raises RdcError(RDC_E_NONFINITE) if a step
+        produced a non-finite value since the last write, unless
+        `allow_nonfinite`."""
+        pu, pv, s = rdc_current(self.ctx)
+        if s == RDC_E_NONFINITE and not allow_nonfinite:
+            raise RdcError(s, rdc_last_error(self.ctx))
         pick = {p.data_ptr(): p for p in self.planes[:4]}
         return pick[pu][:, : self.nx], pick[pv][:, : self.nx]
 

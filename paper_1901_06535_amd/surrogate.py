@@ -618,8 +618,8 @@ class CoarseStepper:
         if self.ckpt_t is not None:
             self.log.append((self.now, disks))
 
-    def current(self):
-        return self.sim.current()
+    def current(self, allow_nonfinite: bool = False):
+        return self.sim.current(allow_nonfinite)
 
     def read(self):
         return self.sim.read()
@@ -632,11 +632,12 @@ class CoarseStepper:
         rdc.rdc_copy(dv.data_ptr(), sv.data_ptr(), nb, s)
 
     def _copy_state(self, dst: "rdc.Sim", src: "rdc.Sim"):
-        (du, dv), (su, sv) = dst.current(), src.current()
+        du, dv = dst.current(allow_nonfinite=True)
+        su, sv = src.current(allow_nonfinite=True)
         self._copy(du, dv, su, sv)
 
     def _checkpoint(self):
-        u, v = self.sim.current()
+        u, v = self.sim.current(allow_nonfinite=True)
         self._copy(self.ckpt[0], self.ckpt[1], u, v)
         self.ckpt_t = self.now
         self.log = []
@@ -644,7 +645,7 @@ class CoarseStepper:
 
     def _rollback_and_replay(self, until: int):
         """Reset the grid to the checkpoint and replay plainly to `until`."""
-        u, v = self.sim.current()
+        u, v = self.sim.current(allow_nonfinite=True)
         self._copy(u, v, self.ckpt[0], self.ckpt[1])
         t = self.ckpt_t
         for when, disks in self.log:
@@ -659,7 +660,7 @@ class CoarseStepper:
         st["discarded_network_steps"] += self._pending
 
     def _network_step(self):
-        u, v = self.sim.current()
+        u, v = self.sim.current(allow_nonfinite=True)
         forward_planes(self.net, self.ws, u.data_ptr(), v.data_ptr(),
                        self.sim.planes[4].data_ptr(), self.pitch, self.plane,
                        predict=(u.data_ptr(), v.data_ptr(), self.params))
@@ -667,14 +668,16 @@ class CoarseStepper:
     def _cells_off(self, a: "rdc.Sim", b: "rdc.Sim") -> int:
         """Cells whose fronts differ by more than one cell between a and b."""
         self.count.zero_()
-        rdc.nn("front_check", a.current()[0].data_ptr(), b.current()[0].data_ptr(), self.pitch,
+        ua = a.current(allow_nonfinite=True)[0]
+        ub = b.current(allow_nonfinite=True)[0]
+        rdc.nn("front_check", ua.data_ptr(), ub.data_ptr(), self.pitch,
                self.nx, self.ny, self.theta, self.count.data_ptr(), self.net.stream.cuda_stream)
         return int(self.count.item())
 
     def _invalid(self, a: "rdc.Sim") -> int:
         """Cells of a's state the plain stepper cannot be trusted to continue."""
         self.count.zero_()
-        u, v = a.current()
+        u, v = a.current(allow_nonfinite=True)
         rdc.nn("state_check", u.data_ptr(), v.data_ptr(), a.planes[4].data_ptr(), self.pitch,
                self.nx, self.ny, self.ulo, 1.5, float(self.params["f"]), self.cmax_valid,
                self.count.data_ptr(), self.net.stream.cuda_stream)

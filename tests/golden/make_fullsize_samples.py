@@ -12,6 +12,9 @@ the waves reached, the four corners and cells on the domain edges):
   masked     (n,) bool    inside the one-cell dilation of the cells the oracle
              ever found Euler-unstable (after step 20)
   first_unstable  int     first such step
+and, for the circuit workload, the oracle's whole arrival map:
+  arr_bits   np.packbits of the row-major (ny, nx) mask of cells that arrived
+  arr_vals   (k,) uint16 their arrival steps in row-major order (all < 65535)
 Only the FP64 oracle and the seeded input generators are called.  Runs for a
 long time (the 16384^2 case: about half an hour on 8 cores).
 
@@ -60,7 +63,7 @@ def sample_cells(run, rng, n_uniform=2048, n_arrived=2048):
     return np.array(sorted(set(pts)), dtype=np.int32)
 
 
-def write(name, wl):
+def write(name, wl, full_arrival=False):
     t0 = time.time()
     run = oracle.Run(wl.u0, wl.v0, wl.phi, wl.params, track_arrival=True, theta=0.5,
                      track_unstable=True, unstable_from=20)
@@ -75,11 +78,17 @@ def write(name, wl):
             xx = np.clip(idx[:, 1] + e - 1, 0, nx - 1)
             arr3[:, d, e] = run.arrival[yy, xx]
     masked = dilate1(run.unstable.astype(bool))[idx[:, 0], idx[:, 1]]
+    extra = {}
+    if full_arrival:
+        hit = run.arrival < oracle.NEVER
+        vals = run.arrival[hit]
+        assert vals.max() < 65535
+        extra = dict(arr_bits=np.packbits(hit.ravel()), arr_vals=vals.astype(np.uint16))
     np.savez_compressed(os.path.join(HERE, name + ".npz"), idx=idx,
                         u=run.u[idx[:, 0], idx[:, 1]], v=run.v[idx[:, 0], idx[:, 1]],
                         arr3=arr3, masked=masked, first_unstable=np.int64(run.first_unstable),
                         finite=np.bool_(np.isfinite(run.u).all() and np.isfinite(run.v).all()),
-                        manifest=np.array(wl.manifest_json()))
+                        manifest=np.array(wl.manifest_json()), **extra)
     print(name, "samples", len(idx), "finite", np.isfinite(run.u).all(),
           "arrived", int((run.arrival < oracle.NEVER).sum()), "first_unstable",
           run.first_unstable, "%.0f s" % (time.time() - t0), flush=True)
@@ -88,7 +97,8 @@ def write(name, wl):
 def main():
     which = sys.argv[1:] or ["circuit", "uniform"]
     if "circuit" in which:
-        write("circuit_4096", inputs.circuit(n=4096, seed=1002, steps=10000, ndisks=256))
+        write("circuit_4096", inputs.circuit(n=4096, seed=1002, steps=10000, ndisks=256),
+              full_arrival=True)
     if "uniform" in which:
         write("uniform_16384", inputs.uniform_random_phi(n=16384, seed=1003, steps=2000))
 

@@ -81,6 +81,29 @@ def test_batch_graph_replays_equal_eager_steps():
     graph_b.close()
 
 
+def test_batch_graph_replay_after_eager_steps_of_odd_launch_count():
+    """Eager steps of an odd number of launches between replays leave the
+    state in the other ping-pong copy; the replay starts from it anyway."""
+    specs, states, disks = _case(seed=11)
+    eager = _batch(specs, states, disks, 8)
+    graph_b = _batch(specs, states, disks, 8)
+    g = graph_b.capture(16)
+    for n_eager in (8, 5, 16, 3):     # 1, 1, 2 and 1 launches of T <= 8
+        eager.step(n_eager)
+        graph_b.step(n_eager)
+        eager.step(16)
+        g.launch()
+        graph_b.synchronize()
+        for i in range(len(specs)):
+            a = eager.read(i)
+            c = graph_b.read(i)
+            assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1]), (n_eager, i)
+    assert graph_b.step_index == eager.step_index
+    g.close()
+    eager.close()
+    graph_b.close()
+
+
 def test_batch_matches_oracle_per_grid():
     specs, states, disks = _case(seed=3)
     b = _batch(specs, states, disks, 8)

@@ -236,9 +236,16 @@ def test_nonfinite_flag_is_raised_and_cleared(dtype, T):
     with pytest.raises(rdc.RdcError) as e:
         s.read()
     assert e.value.status == rdc.RDC_E_NONFINITE
+    # the zero-copy view reports the flag too, and still gives the planes
+    with pytest.raises(rdc.RdcError) as e:
+        s.current()
+    assert e.value.status == rdc.RDC_E_NONFINITE
+    cu, _ = s.current(allow_nonfinite=True)
+    assert not np.isfinite(cu.cpu().numpy()).all()
     s.write(np.zeros_like(u), v)
     s.step(16)
     s.read()   # flag cleared by the fresh state
+    s.current()
     s.close()
 
 

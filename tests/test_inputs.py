@@ -36,6 +36,22 @@ def test_circuit_map_values_and_stimuli():
                                                 ndisks=64).manifest_json()
 
 
+def test_circuit_disk_schedule_spans_the_run_and_keeps_spacing():
+    """Input disks land at steps spread over the whole run (not only at its
+    start) and every pair, earlier or later, keeps the space-time spacing."""
+    wl = inputs.circuit(n=4096, seed=1002, steps=10000, ndisks=256)
+    t = np.array([s.step for s in wl.stimuli])
+    assert len(t) == 256 and list(t) == sorted(t)
+    # quartiles of a uniform sample of 256 from [0, 10,000) lie within +-800
+    # of 2,500 / 5,000 / 7,500 with overwhelming probability
+    q = np.percentile(t, [25, 50, 75])
+    assert np.all(np.abs(q - np.array([2500, 5000, 7500])) < 800), q
+    assert t[-1] > 9000
+    for i, a in enumerate(wl.stimuli):
+        for b in wl.stimuli[i + 1:]:
+            assert inputs.spacing_ok(a.step, a.cx, a.cy, b.step, b.cx, b.cy)
+
+
 def test_circuit_channels_join_across_tiles():
     """Every motif puts its channel on the tile centre lines, so a channel that
     reaches a tile edge does so at the centre band of that edge."""
