@@ -211,8 +211,9 @@ def bench_plain(args):
         T, rows = args.T, args.rows
         tune = {}
     else:
-        rec = sim.autotune(Ts=(args.T,) if args.T else (6, 8, 9, 10, 11, 12),
-                           rows=(args.rows,) if args.rows else (48, 56, 64, 80),
+        rec = sim.autotune(Ts=(args.T,) if args.T else (6, 7, 8, 9, 10, 11, 12),
+                           rows=(args.rows,) if args.rows else (48, 56, 64, 80,
+                                                                rdc.RDC_TILE_STREAM),
                            launches=24 if wl.nx > 8192 else 48, use_cache=False)
         T, rows, tune = rec["T"], rec["rows"], rec["table"]
     sim.set_block(T)
@@ -240,8 +241,10 @@ def bench_plain(args):
     flops = FLOP_PER_UPDATE * cells * T
     achieved_tf = flops / t_k / 1e12
     achieved_bw = BYTES_PER_CELL_LAUNCH * cells / t_k / 1e9
-    key = "stepT_T%d_r%d_%dx%d" % (T, rows, wl.nx, wl.ny)
-    traf = load_traffic(key)
+    from paper_1901_06535_amd.profile_kernels import traffic_key
+    kname = ("k_stream<T=%d>" % T) if rows == rdc.RDC_TILE_STREAM else (
+        "k_stepT<T=%d,rows=%d>" % (T, rows))
+    traf = load_traffic(traffic_key(kname, wl.nx))
     alu = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP32_ALU_PEAK_TFLOPS,
            "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_ALU_PEAK_TFLOPS, 4),
            "traffic": traf["bytes_per_launch"] if traf else None}
@@ -270,7 +273,7 @@ def bench_plain(args):
         "config": {"workload": label, "grid": [wl.nx, wl.ny], "steps_per_run": wl.steps,
                    "stimuli": len(wl.stimuli), "steps_per_launch": T, "tile_rows": rows,
                    "parallelism": "single GPU"},
-        "roofline": dict(roof, kernel="k_stepT<T=%d,rows=%d>" % (T, rows),
+        "roofline": dict(roof, kernel=kname,
                          launch_ms=round(1e3 * t_k, 4),
                          traffic_GBs=round(traf["bytes_per_launch"] / t_k / 1e9, 1) if traf else None,
                          algorithmic="%d FLOP/update x %d updates; %d B/cell x %d cells"
@@ -518,7 +521,7 @@ def bench_surrogate(args):
         l_per += sg.loss_and_grad(net, ev.ws, u, v, ut, vt, ev.pitch, ev.plane)
     ev.close()
 
-    wl = inputs.circuit(n=2048, seed=1005, steps=50000, ndisks=64, tile=256)
+    wl = inputs.circuit(n=2048, seed=1005, steps=50000, ndisks=64, tile=256, disk_order="time")
     zeros = torch.zeros((wl.ny, wl.nx), dtype=torch.float32, device="cuda")
     # plain stepper on the same schedule
     sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")

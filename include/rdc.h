@@ -148,12 +148,17 @@ rdc_status rdc_read(rdc_ctx *ctx, void *u, void *v, int64_t pitch, rdc_where whe
  * (FP64). */
 rdc_status rdc_set_block(rdc_ctx *ctx, int32_t T);
 
-/* Rows of a temporal-blocking tile: 0 (auto: 56 rows) or one of the
- * supported tile heights reported by rdc_tile_rows_supported (the Python
- * autotuner times them on the grid's shape).  Errors: RDC_E_INVAL. */
+/* How launches of several steps are laid out on chip (the result does not
+ * depend on it): 0 (auto: LDS tiles of 56 rows), one of the LDS tile heights
+ * 48, 56, 64, 80, or RDC_TILE_STREAM: every wave walks a 256-column strip
+ * down a segment of rows, carrying all T steps of each row in registers
+ * (FP32, T = 2..9; other launches, FP64, and launches with an arrival map
+ * or timelapse attached use 56-row tiles).  The Python autotuner times the
+ * choices on the grid's shape.  Errors: RDC_E_INVAL. */
+#define RDC_TILE_STREAM 1
 rdc_status rdc_set_tile_rows(rdc_ctx *ctx, int32_t rows);
 
-/* Non-zero if `rows` is a tile height rdc_set_tile_rows accepts. */
+/* Non-zero if `rows` is a value rdc_set_tile_rows accepts (other than 0). */
 int32_t rdc_tile_rows_supported(int32_t rows);
 
 /* Device addresses of the planes that hold the current u and v: a zero-copy

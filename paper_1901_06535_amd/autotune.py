@@ -1,8 +1,9 @@
-"""Autotuner for the stepper's launch shape: steps per launch T and tile
-height (rows) of the temporal-blocking kernels.
+"""Autotuner for the stepper's launch shape: steps per launch T and the
+layout of the temporal-blocking kernels (LDS tile height, or the
+register-resident row pipelines, rows = 1).
 
 Throughput depends on the grid's shape (how its width and height divide into
-256-column x rows-high tiles, how many tiles each XCD gets) and on the chip,
+256-column tiles or strips, how many of them each XCD gets) and on the chip,
 not on the data, so a choice is timed once per (GPU architecture, stepper
 sources, shape) and cached as JSON.  Timing uses HIP events on the
 stream over whole launches of each candidate, after a warm-up launch, on a
@@ -21,7 +22,10 @@ from typing import Dict, Iterable, Optional, Sequence, Tuple
 from .profile_kernels import source_hash
 
 DEFAULT_T = (4, 6, 8, 9, 10, 11, 12)
-DEFAULT_ROWS = (48, 56, 64, 80)
+# LDS tile heights, and 1 = the row-pipeline kernel (rdc.RDC_TILE_STREAM)
+DEFAULT_ROWS = (48, 56, 64, 80, 1)
+# Most steps per launch the row-pipeline kernel takes (FP32 only).
+MAX_T_STREAM = 9
 # Most steps per launch the library's tile kernels take, per precision
 # (rdc_set_block; the batched kernels are FP32).
 MAX_T = {"fp32": 12, "fp64": 8}
@@ -83,6 +87,8 @@ def _search(step, set_shape, stream, Ts: Iterable[int], rows: Iterable[int],
     table = {}
     for T in Ts:
         for r in rows:
+            if r == 1 and T > MAX_T_STREAM:
+                continue                      # such launches would run as 56-row tiles
             table["T%d_r%d" % (T, r)] = _time(step, set_shape, stream, T, r, launches)
     best = min(table, key=table.get)
     T, r = (int(x) for x in best[1:].split("_r"))
@@ -103,6 +109,8 @@ def tune_sim(sim, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = DEFAULT_R
         scratch = rdc.Sim(sim.nx, sim.ny, sim.params, sim.dtype, device=sim.device,
                           stream=sim.stream)
         Ts = [T for T in Ts if T <= MAX_T[sim.dtype]]
+        if sim.dtype != "fp32":
+            rows = [r for r in rows if r != 1]
 
         def set_shape(T, r):
             scratch.set_block(T)

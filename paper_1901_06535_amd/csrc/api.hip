@@ -80,20 +80,7 @@ const char* check_params(const rdc_params& p) {
 
 template <typename Real>
 rdc::Consts<Real> consts(const rdc_params& p) {
-    // Formed in double, in the order of the scheme's definition:
-    // c1 = dt/eps, c2 = dt*D_u/(dx*dx).
-    const double c1 = p.dt / p.eps;
-    const double c2 = p.dt * p.D_u / (p.dx * p.dx);
-    rdc::Consts<Real> k;
-    k.c1 = static_cast<Real>(c1);
-    k.c2 = static_cast<Real>(c2);
-    k.f = static_cast<Real>(p.f);
-    k.q = static_cast<Real>(p.q);
-    k.dt = static_cast<Real>(p.dt);
-    k.k0 = static_cast<Real>(1.0 + c1 - 4.0 * c2);
-    k.c1f = static_cast<Real>(c1 * p.f);
-    k.omdt = static_cast<Real>(1.0 - p.dt);
-    return k;
+    return rdc::make_consts<Real>(p.eps, p.f, p.q, p.D_u, p.dt, p.dx);
 }
 
 template <typename Real>
@@ -317,6 +304,8 @@ rdc_status rdc_step(rdc_ctx* c, int64_t n) {
     DeviceGuard g(c->device);
     const int T = c->T > 0 ? c->T : auto_block(c);
     const int rows = c->tile_rows > 0 ? c->tile_rows : rdc::tile_rows_default();
+    // LDS tile height for the launches the row pipelines do not take.
+    const int tile_rows = rows == RDC_TILE_STREAM ? rdc::tile_rows_default() : rows;
     const bool f64 = c->dtype == RDC_FP64;
     // ceil(n / T) launches of near-equal length (n = 9, T = 8 runs 5 + 4,
     // not 8 + 1): the launch count is the least possible, and no short
@@ -329,9 +318,12 @@ rdc_status rdc_step(rdc_ctx* c, int64_t n) {
         if (k == 1)
             e = f64 ? rdc::launch_step1(step_args<double>(c), c->stream)
                     : rdc::launch_step1(step_args<float>(c), c->stream);
+        else if (rows == RDC_TILE_STREAM && !f64 && rdc::stream_supported(k) && !c->arrival &&
+                 !c->tl)
+            e = rdc::launch_stream(step_args<float>(c), k, c->stream);
         else
-            e = f64 ? rdc::launch_stepT(step_args<double>(c), k, rows, c->stream)
-                    : rdc::launch_stepT(step_args<float>(c), k, rows, c->stream);
+            e = f64 ? rdc::launch_stepT(step_args<double>(c), k, tile_rows, c->stream)
+                    : rdc::launch_stepT(step_args<float>(c), k, tile_rows, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->cur ^= 1;
         c->step += k;
@@ -368,11 +360,13 @@ rdc_status rdc_set_block(rdc_ctx* c, int32_t T) {
     return RDC_OK;
 }
 
-int32_t rdc_tile_rows_supported(int32_t rows) { return rdc::tile_rows_supported(rows) ? 1 : 0; }
+int32_t rdc_tile_rows_supported(int32_t rows) {
+    return (rows == RDC_TILE_STREAM || rdc::tile_rows_supported(rows)) ? 1 : 0;
+}
 
 rdc_status rdc_set_tile_rows(rdc_ctx* c, int32_t rows) {
     if (!c) return RDC_E_INVAL;
-    if (rows != 0 && !rdc::tile_rows_supported(rows))
+    if (rows != 0 && !rdc_tile_rows_supported(rows))
         return fail(c, RDC_E_INVAL, "unsupported tile height");
     c->tile_rows = rows;
     return RDC_OK;

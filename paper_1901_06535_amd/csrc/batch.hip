@@ -203,19 +203,8 @@ const char* check_sim_params(const rdc_params& p) {
 }
 
 rdc::Consts<float> sim_consts(const rdc_params& p) {
-    // Same constants, in the same order, as the single-grid path.
-    const double c1 = p.dt / p.eps;
-    const double c2 = p.dt * p.D_u / (p.dx * p.dx);
-    rdc::Consts<float> k;
-    k.c1 = static_cast<float>(c1);
-    k.c2 = static_cast<float>(c2);
-    k.f = static_cast<float>(p.f);
-    k.q = static_cast<float>(p.q);
-    k.dt = static_cast<float>(p.dt);
-    k.k0 = static_cast<float>(1.0 + c1 - 4.0 * c2);
-    k.c1f = static_cast<float>(c1 * p.f);
-    k.omdt = static_cast<float>(1.0 - p.dt);
-    return k;
+    // Same constants as the single-grid path.
+    return rdc::make_consts<float>(p.eps, p.f, p.q, p.D_u, p.dt, p.dx);
 }
 
 struct Dev {

@@ -44,10 +44,30 @@ hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s
 // The same for FP64 (tiles of 128 columns, 2 cells per lane).
 hipError_t launch_stepT(const StepArgs<double>& a, int T, int rows, hipStream_t s);
 bool tile_rows_supported(int rows);
+// The tile kernels of one height (8 waves x R rows), FP32 and FP64; defined
+// in tiles_impl.h and instantiated in tiles_r<R>.hip for R = 6, 7, 8, 10.
+template <int R>
+hipError_t launch_tiles(const StepArgs<float>& a, int T, hipStream_t s);
+template <int R>
+hipError_t launch_tiles(const StepArgs<double>& a, int T, hipStream_t s);
 // Most rows a grid may have: the one-step kernel's launch grid covers
 // kStep1Rows rows per block row, at most 65535 block rows.
 int max_rows();
 int tile_rows_default();
+
+// T forward-Euler steps per launch by register-resident row pipelines
+// (FP32, one wave per 256-column strip and segment of rows; no LDS tiles).
+// T in 2..kMaxStream; results bit-identical to launch_step1 and launch_stepT.
+constexpr int kMaxStream = 9;
+struct StreamGeom {
+    int bx;        // output columns per strip (a multiple of 4)
+    int nstrips;   // strips across the grid
+    int seg_rows;  // output rows per segment
+    int items;     // strips x segments, one wave each
+    int per_xcd;   // workgroups per XCD
+};
+bool stream_supported(int T);
+hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s);
 
 // Catalytic stimulation: u := 1 on up to kMaxDisks disks per launch.
 constexpr int kMaxDisks = 64;

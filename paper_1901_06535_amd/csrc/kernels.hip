@@ -6,14 +6,8 @@
 //            north/centre/south rows of u in registers, so u, v and phi are
 //            each read from HBM once and u', v' written once (20 B per
 //            FP32 cell-update, 40 B in FP64).
-//   k_stepT  T steps per launch (FP32): a workgroup of 8 waves loads a
-//            256-column by EY-row tile of u (into LDS), v and phi (into
-//            registers) including a halo mirrored at the domain edges, runs T
-//            steps on chip with the valid region shrinking by one cell per
-//            step, and writes the (256-2*HX) x (EY-2*T) interior.  Each wave
-//            owns whole 256-cell tile rows (64 lanes x 4 cells), so the east /
-//            west neighbours cross lanes by DPP row shifts and only the
-//            north / south rows go through LDS.
+// The T-step kernels are in tiles_impl.h (LDS tiles, one translation unit
+// per tile height) and stream.hip (row pipelines).
 #include "kernels.h"
 #include "tile.h"
 
@@ -130,32 +124,6 @@ __global__ __launch_bounds__(kStep1Threads) void k_step1(StepArgs<Real> a) {
     if (bad) *a.flag = 1;
 }
 
-// ---------------------------------------------------------------- T steps
-
-template <int T, int R, bool OUT>
-__global__ __launch_bounds__(kTileWaves * 64, (tile_waves_per_simd<R, OUT>()))
-void k_stepT(StepArgs<float> a, int tiles_x, int ntiles, int per_xcd) {
-    __shared__ float4 lds[kTileWaves * R][64];
-    // Workgroups are dealt to the 8 XCDs round-robin; renumber so that each
-    // XCD walks a contiguous run of the row-major tile order: concurrent
-    // tiles of one XCD share halo cells in its L2, and their loads sweep long
-    // contiguous row segments.  (A column-major walk measured slower.)
-    const int b = blockIdx.x;
-    const int tile = (b & 7) * per_xcd + (b >> 3);
-    if (tile >= ntiles) return;
-    step_tile<T, R, OUT>(a, tile % tiles_x, tile / tiles_x, lds);
-}
-
-template <int T, int R, bool OUT>
-__global__ __launch_bounds__(kTileWaves * 64, (tile_waves_per_simd<R, OUT>()))
-void k_stepT64(StepArgs<double> a, int tiles_x, int ntiles, int per_xcd) {
-    __shared__ double2 lds[kTileWaves * R][64];
-    const int b = blockIdx.x;
-    const int tile = (b & 7) * per_xcd + (b >> 3);   // XCD-contiguous runs, as k_stepT
-    if (tile >= ntiles) return;
-    step_tile64<T, R, OUT>(a, tile % tiles_x, tile / tiles_x, lds);
-}
-
 // ---------------------------------------------------------------- stimulation etc.
 
 template <typename Real>
@@ -242,71 +210,6 @@ hipError_t step1_impl(const StepArgs<Real>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int T, int R>
-hipError_t stepT_impl(const StepArgs<float>& a, hipStream_t s) {
-    constexpr int HX = (T + 3) & ~3;
-    constexpr int BX = kTileCols - 2 * HX;
-    constexpr int BY = kTileWaves * R - 2 * T;
-    const int tiles_x = (a.nx + BX - 1) / BX;
-    const int tiles_y = (a.ny + BY - 1) / BY;
-    const int ntiles = tiles_x * tiles_y;
-    const int per_xcd = (ntiles + 7) / 8;
-    const dim3 grid(8 * per_xcd), block(kTileWaves * 64);
-    if (a.arrival || a.tl)
-        hipLaunchKernelGGL((k_stepT<T, R, true>), grid, block, 0, s, a, tiles_x, ntiles, per_xcd);
-    else
-        hipLaunchKernelGGL((k_stepT<T, R, false>), grid, block, 0, s, a, tiles_x, ntiles, per_xcd);
-    return hipGetLastError();
-}
-
-template <int R>
-hipError_t stepT_rows(const StepArgs<float>& a, int T, hipStream_t s) {
-    switch (T) {
-        case 2: return stepT_impl<2, R>(a, s);
-        case 3: return stepT_impl<3, R>(a, s);
-        case 4: return stepT_impl<4, R>(a, s);
-        case 5: return stepT_impl<5, R>(a, s);
-        case 6: return stepT_impl<6, R>(a, s);
-        case 7: return stepT_impl<7, R>(a, s);
-        case 8: return stepT_impl<8, R>(a, s);
-        case 9: return stepT_impl<9, R>(a, s);
-        case 10: return stepT_impl<10, R>(a, s);
-        case 11: return stepT_impl<11, R>(a, s);
-        case 12: return stepT_impl<12, R>(a, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <int T, int R>
-hipError_t stepT64_impl(const StepArgs<double>& a, hipStream_t s) {
-    using G = TileGeom64<T, R>;
-    const int tiles_x = (a.nx + G::BX - 1) / G::BX;
-    const int tiles_y = (a.ny + G::BY - 1) / G::BY;
-    const int ntiles = tiles_x * tiles_y;
-    const int per_xcd = (ntiles + 7) / 8;
-    const dim3 grid(8 * per_xcd), block(kTileWaves * 64);
-    if (a.arrival || a.tl)
-        hipLaunchKernelGGL((k_stepT64<T, R, true>), grid, block, 0, s, a, tiles_x, ntiles, per_xcd);
-    else
-        hipLaunchKernelGGL((k_stepT64<T, R, false>), grid, block, 0, s, a, tiles_x, ntiles,
-                           per_xcd);
-    return hipGetLastError();
-}
-
-template <int R>
-hipError_t stepT64_rows(const StepArgs<double>& a, int T, hipStream_t s) {
-    switch (T) {
-        case 2: return stepT64_impl<2, R>(a, s);
-        case 3: return stepT64_impl<3, R>(a, s);
-        case 4: return stepT64_impl<4, R>(a, s);
-        case 5: return stepT64_impl<5, R>(a, s);
-        case 6: return stepT64_impl<6, R>(a, s);
-        case 7: return stepT64_impl<7, R>(a, s);
-        case 8: return stepT64_impl<8, R>(a, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 template <typename Real>
 hipError_t stimulate_impl(Real* u, int64_t pitch, int nx, int ny, const Disks& d,
                           int32_t* arrival, int64_t apitch, int step, hipStream_t s) {
@@ -347,24 +250,24 @@ bool tile_rows_supported(int rows) {
 int tile_rows_default() { return 56; }
 int max_rows() { return 65535 * kStep1Rows; }
 
-hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s) {
+// Tile heights are 8 rows per wave times R; each R's kernels live in their
+// own translation unit (tiles_r<R>.hip).
+template <typename Real>
+hipError_t stepT_any(const StepArgs<Real>& a, int T, int rows, hipStream_t s) {
     switch (rows) {
-        case 48: return stepT_rows<6>(a, T, s);
-        case 56: return stepT_rows<7>(a, T, s);
-        case 64: return stepT_rows<8>(a, T, s);
-        case 80: return stepT_rows<10>(a, T, s);
+        case 48: return launch_tiles<6>(a, T, s);
+        case 56: return launch_tiles<7>(a, T, s);
+        case 64: return launch_tiles<8>(a, T, s);
+        case 80: return launch_tiles<10>(a, T, s);
         default: return hipErrorInvalidValue;
     }
 }
 
+hipError_t launch_stepT(const StepArgs<float>& a, int T, int rows, hipStream_t s) {
+    return stepT_any(a, T, rows, s);
+}
 hipError_t launch_stepT(const StepArgs<double>& a, int T, int rows, hipStream_t s) {
-    switch (rows) {
-        case 48: return stepT64_rows<6>(a, T, s);
-        case 56: return stepT64_rows<7>(a, T, s);
-        case 64: return stepT64_rows<8>(a, T, s);
-        case 80: return stepT64_rows<10>(a, T, s);
-        default: return hipErrorInvalidValue;
-    }
+    return stepT_any(a, T, rows, s);
 }
 
 hipError_t launch_stimulate(float* u, int64_t pitch, int nx, int ny, const Disks& d,

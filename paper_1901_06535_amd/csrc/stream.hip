@@ -1,0 +1,340 @@
+// stream.hip -- T forward-Euler steps of the Oregonator (Sec. 2, Eq. (1)) per
+// launch, FP32, by row pipelines held in registers.
+//
+// Each wave owns a strip of 256 columns (64 lanes x 4 adjacent cells) and a
+// segment of rows, and walks down the segment one row per tick.  In every
+// tick it first loads one new row of u, v and phi (a few rows ahead of use),
+// then advances each time level t = 1..T by one row: level t turns rows
+// rho-1, rho, rho+1 of u at step t-1 into row rho of u and v at step t,
+// where rho = tick - t + 1 (a skew of one row per level, so level t reads
+// the row level t-1 finished earlier in the same tick).  The last level's
+// row is written out.  Every intermediate state stays in registers:
+//   - each level t keeps the three rows of u^(t-1) its five-node sum needs
+//     (row index mod 3; level 1 keeps u^0 rows mod 6 to leave room for the
+//     loads in flight),
+//   - v and c1*phi of the rows in flight sit in 12 row slots (row index mod
+//     12); each level updates v in place as the row passes it.
+// The tick loop is unrolled by 12, so every slot index is a compile-time
+// constant and no value is ever moved between registers.  There are no LDS
+// tiles and no barriers: waves run independently.  East / west neighbours
+// cross lanes by DPP; the strip's outer columns are a halo of width >= T
+// that goes stale by one column per level and is recomputed by the
+// neighbouring strip, and a segment is extended by T rows above and below.
+// Halo rows and columns beyond the domain are loaded mirrored (the even
+// extension evolves exactly like the interior), so no level needs edge code.
+// Every cell goes through cell_update, so the result is bit-identical to the
+// one-step kernel and to the LDS tile kernel at any launch shape.
+//
+// Every tick issues the same memory instructions whatever the row or lane
+// (rows past the segment and lanes outside the output use buffer offsets
+// past the row's end, which the hardware drops), so the compiler can count
+// outstanding loads exactly and wait only for the row a level is about to
+// use.  Waves whose strip reaches past a domain edge take a second copy of
+// the loop that loads and stores cell by cell.
+#include "kernels.h"
+#include "tile.h"
+
+namespace rdc {
+namespace {
+
+using namespace dev;
+
+constexpr int kStreamWaves = 4;   // waves per workgroup (independent pipelines)
+constexpr int kUnroll = 12;       // ticks per unrolled loop body
+constexpr int kRowSlots = 12;     // v, c1*phi rows held: row index mod 12
+constexpr int kU0Slots = 6;       // u^0 rows held by level 1: row index mod 6
+// A row is loaded this many ticks before its first use (at most 3: the u^0
+// slots hold rows i-1 .. i+1+kAhead); fewer when T is large, so that the
+// row slots still hold every row in flight.  RDC_STREAM_AHEAD caps it (a
+// build-time tunable).
+#ifndef RDC_STREAM_AHEAD
+#define RDC_STREAM_AHEAD 3
+#endif
+template <int T>
+constexpr int stream_ahead() {
+    return (kRowSlots - 1 - T) < RDC_STREAM_AHEAD ? (kRowSlots - 1 - T) : RDC_STREAM_AHEAD;
+}
+// A buffer offset past any row (rows are shorter than 2 GiB): the access is
+// dropped.
+constexpr int kOff = static_cast<int>(0x80000000u);
+
+constexpr int md(int a, int m) { return ((a % m) + m) % m; }
+
+// Column halo on the left of the strip: T rounded up to whole lanes, so the
+// strip's loads and stores stay 16-byte aligned.
+template <int T>
+constexpr int stream_hx() { return (T + 3) & ~3; }
+
+// v and c1*phi of a row stay in their slot from the load until the last
+// level is done with the row: the slot is reloaded kRowSlots - 1 - kAhead
+// ticks after the row's first use.
+template <int T>
+constexpr bool stream_fits() {
+    return T >= 2 && stream_ahead<T>() >= 1 && stream_ahead<T>() <= kU0Slots - 3;
+}
+
+struct Lane {
+    int gx;          // first global column of this lane's 4 cells
+    int xb[4];       // byte offsets of its 4 columns, mirrored at the domain edges
+    int so[4];       // byte offsets of its 4 output cells, or kOff where not stored
+    int so4;         // byte offset of its 16-byte output word, or kOff
+    uint64_t out;    // lanes holding output cells
+};
+
+template <int T, bool EDGE>
+__device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const Lane& ln,
+                                                int y0, int y1) {
+    constexpr int kAhead = stream_ahead<T>();
+    const int ny = a.ny;
+    const int64_t P = a.pitch;
+    const int row_bytes = static_cast<int>(P * 4);
+    const int i0 = y0 - T + 1;                 // first tick: level 1 on row y0 - T + 1
+    const int i_end = y1 + T - 1;              // ticks [i0, i_end)
+    // k0 kept in a VGPR: an FMA reads one scalar operand at most.
+    Consts<float> k = a.k;
+    k.k0 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(k.k0), 0xe4, 0xf, 0xf, false));
+
+    // Every level runs on every tick, also before its first row and after
+    // its last (levels t and t+1 start and stop together apart from one row
+    // at either end, so such a row of u^t is never read by level t+1, and a
+    // row's v is not touched by any level after it left the range of rows
+    // that level owns); only level T's output is checked and written, and
+    // only where it ran on a row of the segment.  Slots start at zero.
+    float u0[kU0Slots][4] = {};                // u^0 rows (level 1's window)
+    float uw[T + 1][3][4] = {};                // uw[t]: rows of u^(t-1), t >= 2
+    float vr[kRowSlots][4] = {};               // v of rows in flight
+    float pr[kRowSlots][4] = {};               // c1*phi (raw phi until its first use)
+
+    // Load row r of u (and of v, phi); rows past the last one any level
+    // needs (i_end) read nothing.
+    auto load_row = [&](int r, float (&uu)[4], float (&vv)[4], float (&pp)[4],
+                        bool with_vp) __attribute__((always_inline)) {
+        const int64_t off = (int64_t)reflect_index(r, ny) * P;
+        const int nb = r <= i_end ? row_bytes : 0;
+        const auto ru = row_rsrc(a.u + off, nb);
+        const auto rv = row_rsrc(a.v + off, nb);
+        const auto rp = row_rsrc(a.phi + off, nb);
+        if (!EDGE) {
+            const float4 t = buf_load4(ru, ln.xb[0]);
+            uu[0] = t.x; uu[1] = t.y; uu[2] = t.z; uu[3] = t.w;
+            if (with_vp) {
+                const float4 w = buf_load4(rv, ln.xb[0]);
+                vv[0] = w.x; vv[1] = w.y; vv[2] = w.z; vv[3] = w.w;
+                const float4 p = buf_load4(rp, ln.xb[0]);
+                pp[0] = p.x; pp[1] = p.y; pp[2] = p.z; pp[3] = p.w;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                uu[c] = buf_load1(ru, ln.xb[c]);
+                if (with_vp) {
+                    vv[c] = buf_load1(rv, ln.xb[c]);
+                    pp[c] = buf_load1(rp, ln.xb[c]);
+                }
+            }
+        }
+    };
+
+    // Rows the first ticks need: u^0 rows i0-1 .. i0+kAhead, v and phi rows
+    // i0 .. i0+kAhead (relative row j lives in slot j mod 6 / j mod 12).
+    load_row(i0 - 1, u0[md(-1, kU0Slots)], vr[md(-1, kRowSlots)], pr[md(-1, kRowSlots)], false);
+#pragma unroll
+    for (int j = 0; j <= kAhead; ++j) load_row(i0 + j, u0[j], vr[j], pr[j], true);
+
+    uint64_t bad = 0;
+    for (int ib = i0; ib < i_end; ib += kUnroll) {
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+            const int i = ib + s;
+            // The row first needed kAhead ticks from now.  Its slots held row
+            // i + 1 + kAhead - 6 (u^0) and - 12 (v, phi), which every level
+            // has finished with.
+            load_row(i + 1 + kAhead, u0[md(s + 1 + kAhead, kU0Slots)],
+                     vr[md(s + 1 + kAhead, kRowSlots)], pr[md(s + 1 + kAhead, kRowSlots)], true);
+            // phi of row i enters level 1 now: scale it once.
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                pr[md(s, kRowSlots)][c] = scaled_phi(pr[md(s, kRowSlots)][c], k);
+
+            float un[4];
+            // level T runs on a row of the segment (uniform)
+            const bool live_T = i >= i0 + 2 * T - 2 && i < i_end;
+#pragma unroll
+            for (int t = 1; t <= T; ++t) {
+                const int rs = md(s - t + 1, kRowSlots);           // slot of row rho = i - t + 1
+                const float* n;
+                const float* c;
+                const float* so;
+                if (t == 1) {
+                    n = u0[md(s - 1, kU0Slots)];
+                    c = u0[md(s, kU0Slots)];
+                    so = u0[md(s + 1, kU0Slots)];
+                } else {
+                    n = uw[t][md(s - t, 3)];
+                    c = uw[t][md(s - t + 1, 3)];
+                    so = uw[t][md(s - t + 2, 3)];
+                }
+                const float west = from_west_lane(c[3]);
+                const float east = from_east_lane(c[0]);
+                // (west and east enter as a sum; the lane-shifted value goes
+                // first so the shift folds into the add)
+                cell_update(c[0], c[1], west, n[0], so[0], vr[rs][0], pr[rs][0], k, un[0],
+                            vr[rs][0]);
+                cell_update(c[1], c[0], c[2], n[1], so[1], vr[rs][1], pr[rs][1], k, un[1],
+                            vr[rs][1]);
+                cell_update(c[2], c[1], c[3], n[2], so[2], vr[rs][2], pr[rs][2], k, un[2],
+                            vr[rs][2]);
+                cell_update(c[3], c[2], east, n[3], so[3], vr[rs][3], pr[rs][3], k, un[3],
+                            vr[rs][3]);
+                if (t < T) {
+                    // row rho of u^t: level t+1's newest row
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) uw[t < T ? t + 1 : T][md(s - t + 1, 3)][e] = un[e];
+                } else if (live_T) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool ok = __builtin_isfinite(un[e]) && __builtin_isfinite(vr[rs][e]);
+                        bad |= __builtin_amdgcn_ballot_w64(!ok);
+                    }
+                }
+            }
+            // Row i - T + 1 of u^T and v^T, written where level T ran on it.
+            const int rs = md(s - T + 1, kRowSlots);
+            const int64_t off = (int64_t)min(max(i - T + 1, 0), ny - 1) * P;
+            const int nb = live_T ? row_bytes : 0;
+            const auto ro = row_rsrc(a.u_out + off, nb);
+            const auto rv = row_rsrc(a.v_out + off, nb);
+            if (!EDGE) {
+                buf_store4(ro, ln.so4, un[0], un[1], un[2], un[3]);
+                buf_store4(rv, ln.so4, vr[rs][0], vr[rs][1], vr[rs][2], vr[rs][3]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    buf_store1(ro, ln.so[e], un[e]);
+                    buf_store1(rv, ln.so[e], vr[rs][e]);
+                }
+            }
+        }
+    }
+    if (bad & ln.out) {
+        if ((threadIdx.x & 63) == __builtin_ctzll(ln.out)) *a.flag = 1;
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(kStreamWaves * 64, 2)
+void k_stream(StepArgs<float> a, StreamGeom g) {
+    static_assert(stream_fits<T>(), "T too large for the row slots");
+    constexpr int HX = stream_hx<T>();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Workgroups are dealt to the 8 XCDs round-robin: renumber so that each
+    // XCD takes a contiguous run of work items (neighbouring strips of the
+    // same rows, whose halo columns then meet in that XCD's L2).
+    const int b = blockIdx.x;
+    const int wg = (b & 7) * g.per_xcd + (b >> 3);
+    const int item = wg * kStreamWaves + wave;
+    if (item >= g.items) return;
+    const int strip = item % g.nstrips;
+    const int seg = item / g.nstrips;
+    const int nx = a.nx;
+
+    const int x_out0 = strip * g.bx;           // first output column
+    const int x_load0 = x_out0 - HX;           // first loaded column
+    Lane ln;
+    ln.gx = x_load0 + 4 * lane;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ln.xb[c] = 4 * reflect_index(ln.gx + c, nx);
+    const bool out_lane = lane >= HX / 4 && lane < (HX + g.bx) / 4 && ln.gx < nx;
+    ln.so4 = out_lane ? 4 * ln.gx : kOff;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ln.so[c] = out_lane && ln.gx + c < nx ? 4 * (ln.gx + c) : kOff;
+    ln.out = __builtin_amdgcn_ballot_w64(out_lane);
+
+    const int y0 = seg * g.seg_rows;
+    const int y1 = min(y0 + g.seg_rows, a.ny);   // output rows [y0, y1)
+    // Interior strips load and store 16-byte words; a strip that reaches
+    // past the left or right edge goes cell by cell.
+    if (x_load0 >= 0 && x_load0 + 256 <= nx)
+        stream_pipeline<T, false>(a, ln, y0, y1);
+    else
+        stream_pipeline<T, true>(a, ln, y0, y1);
+}
+
+// Items (strip, segment) for the streaming kernel: strips of `bx` output
+// columns; segments of near-equal height, as many as keep lowest the rows
+// walked per round of resident waves (`slots` waves at a time).
+StreamGeom stream_geom(int nx, int ny, int T, int bx, int slots) {
+    StreamGeom g{};
+    g.bx = bx;
+    g.nstrips = (nx + bx - 1) / bx;
+    int best_rows = ny;
+    double best = -1.0;
+    for (int nseg = 1; nseg <= ny; ++nseg) {
+        const int rows = (ny + nseg - 1) / nseg;
+        const int64_t items = (int64_t)g.nstrips * ((ny + rows - 1) / rows);
+        const int64_t rounds = (items + slots - 1) / slots;
+        // ticks a wave walks: rows + 2T - 2, in whole unrolled loop bodies
+        const int64_t ticks = (rows + 2 * T - 2 + kUnroll - 1) / kUnroll * kUnroll;
+        const double cost = (double)rounds * ticks;
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_rows = rows;
+        }
+        if (items > 64LL * slots) break;
+    }
+    g.seg_rows = best_rows;
+    g.items = g.nstrips * ((ny + best_rows - 1) / best_rows);
+    const int wgs = (g.items + kStreamWaves - 1) / kStreamWaves;
+    g.per_xcd = (wgs + 7) / 8;
+    return g;
+}
+
+int device_slots() {
+    // Resident waves when every CU holds two 4-wave workgroups (the launch
+    // bounds ask for two waves per SIMD).
+    static int cached_dev = -1, cached = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 2048;
+    if (dev != cached_dev) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        cached = cus * 4 * 2;
+        cached_dev = dev;
+    }
+    return cached;
+}
+
+template <int T>
+hipError_t stream_impl(const StepArgs<float>& a, hipStream_t s) {
+    constexpr int HX = stream_hx<T>();
+    // Output columns: the loaded 256 less the left halo HX and a right halo
+    // of at least T, kept a multiple of 4.
+    constexpr int bx = (256 - HX - T) & ~3;
+    const StreamGeom g = stream_geom(a.nx, a.ny, T, bx, device_slots());
+    const dim3 grid(8 * g.per_xcd), block(kStreamWaves * 64);
+    hipLaunchKernelGGL((k_stream<T>), grid, block, 0, s, a, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool stream_supported(int T) { return T >= 2 && T <= kMaxStream; }
+
+hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s) {
+    switch (T) {
+        case 2: return stream_impl<2>(a, s);
+        case 3: return stream_impl<3>(a, s);
+        case 4: return stream_impl<4>(a, s);
+        case 5: return stream_impl<5>(a, s);
+        case 6: return stream_impl<6>(a, s);
+        case 7: return stream_impl<7>(a, s);
+        case 8: return stream_impl<8>(a, s);
+        case 9: return stream_impl<9>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace rdc

@@ -218,21 +218,30 @@ def spacing_ok(t: int, x: int, y: int, tj: int, xj: int, yj: int) -> bool:
 
 
 def _spaced_disks(rng: np.random.Generator, active: np.ndarray, steps: int,
-                  ndisks: int) -> List[Stimulus]:
+                  ndisks: int, order: str = "drawn") -> List[Stimulus]:
     """Up to ``ndisks`` r=5 input disks wholly inside the ``active`` cells at
-    steps drawn uniformly from [0, steps): candidates (step, centre) are
-    drawn independently and taken in the order drawn, each kept if it keeps
-    the space-time spacing (``spacing_ok``) with every disk kept so far,
-    earlier or later in time; the kept disks are returned in time order.
-    (Catalysing medium that an earlier wave has left refractory drives
-    forward Euler at dt = 0.001 into divergence.)"""
+    steps drawn uniformly from [0, steps): 8 * ndisks candidates (step,
+    centre) are drawn independently and taken in the order drawn
+    (``order="drawn"``, which spreads the kept disks over the whole run) or
+    in time order (``order="time"``, which fills the budget with the
+    earliest ones), each kept if it keeps the space-time spacing
+    (``spacing_ok``) with every disk kept so far, earlier or later in time;
+    the kept disks are returned in time order.  (Catalysing medium that an
+    earlier wave has left refractory drives forward Euler at dt = 0.001 into
+    divergence.)"""
     fits = _disk_fits(active, STIM_RADIUS)
     fy, fx = np.nonzero(fits)
     cand_t = rng.integers(0, steps, size=8 * ndisks)
     cand_p = rng.integers(0, fy.size, size=8 * ndisks)
+    if order == "time":
+        pick = np.argsort(cand_t, kind="stable")
+    elif order == "drawn":
+        pick = np.arange(cand_t.size)
+    else:
+        raise ValueError(order)
     kept = []
-    for t, p in zip(cand_t, cand_p):
-        t, y, x = int(t), int(fy[p]), int(fx[p])
+    for c in pick:
+        t, y, x = int(cand_t[c]), int(fy[cand_p[c]]), int(fx[cand_p[c]])
         if all(spacing_ok(t, x, y, tj, xj, yj) for (tj, yj, xj) in kept):
             kept.append((t, y, x))
             if len(kept) == ndisks:
@@ -242,7 +251,8 @@ def _spaced_disks(rng: np.random.Generator, active: np.ndarray, steps: int,
 
 
 def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 256,
-            tile: int = 256, and_phi_gap: float = AND_PHI_GAP) -> Workload:
+            tile: int = 256, and_phi_gap: float = AND_PHI_GAP,
+            disk_order: str = "drawn") -> Workload:
     """Seeded circuit phi map: excitable 16-wide channels (0.054) on an
     inhibitory background (0.2), built from (tile x tile) macro-tiles, each
     holding a straight, cross, corner, diode or AND T-junction motif at a
@@ -250,7 +260,9 @@ def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 2
     channels of neighbouring tiles join.  Up to ``ndisks`` r=5 input disks lie
     wholly inside excitable channels at uniformly random steps in [0, steps),
     spaced so that no disk lands where an earlier disk's wave can already
-    have passed (``_spaced_disks``).  (Catalysing the phi=0.2 background, or
+    have passed (``_spaced_disks``; ``disk_order="time"`` keeps the earliest
+    candidates, which a long run on a small grid needs: its late candidates
+    mostly conflict with early ones).  (Catalysing the phi=0.2 background, or
     re-exciting medium still refractory from an earlier wave, drives forward
     Euler at dt=0.001 into divergence.)"""
     if n % tile:
@@ -267,7 +279,7 @@ def circuit(n: int = 4096, seed: int = 1002, steps: int = 10000, ndisks: int = 2
     lut = np.array([PHI_INHIBITORY, PHI_EXCITABLE, DIODE_PHI_GAP, and_phi_gap],
                    dtype=np.float32)
     phi = lut[lab]
-    stim = _spaced_disks(rng, lab == _CH, steps, ndisks)
+    stim = _spaced_disks(rng, lab == _CH, steps, ndisks, disk_order)
     wl = Workload("circuit_%d" % n, n, n, dict(PARAMS_WORKLOAD), phi,
                   _zeros(n, n), _zeros(n, n), stim, steps, seed)
     wl.extra["motif_counts"] = [int((motifs == i).sum()) for i in range(len(_MOTIFS))]

@@ -1,23 +1,26 @@
 """Fixed launches of each stepper kernel, for hardware-counter runs.
 
-Runs, on the circuit workload's 4096x4096 grid: a few launches of the
-temporal-blocking kernel for every (steps per launch, tile rows) pair the
-benchmark's autotuner may pick; on a 16384x16384 grid: a few launches of the
-FP32 and FP64 one-step kernels and of the FP64 T-step kernel (T=8, 56 and 64
-rows); and three 1 GiB launches of the plain copy kernel (the
-reference reading that scales memory counters to bytes).  Under
+    python3 -m paper_1901_06535_amd.profile_kernels --workload uniform
 
-    rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_1901_06535_amd.profile_kernels
+runs, on the uniform workload's 16384x16384 grid, a few launches of the
+FP32 T-step kernels the benchmark's autotuner may pick (row pipelines, T = 6..9;
+LDS tiles), of the FP32 and FP64 one-step kernels and of the FP64 T-step
+kernel; ``--workload circuit`` runs every FP32 T-step candidate on the
+circuit workload's 4096x4096 grid.  Both end with three 1 GiB launches of the
+plain copy kernel (the reading that scales memory counters to bytes).  Under
+
+    rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_1901_06535_amd.profile_kernels --workload W
 
 each dispatch gets its own counter values.  Prints what it launched.
 
-    python3 -m paper_1901_06535_amd.profile_kernels --summarize FETCH.csv WRITE.csv
+    python3 -m paper_1901_06535_amd.profile_kernels --summarize FETCH.csv WRITE.csv --workload W
 
 turns the two counter runs' CSV files into per-launch HBM bytes: each
 kernel's average FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what
-the same counters read for the 1 GiB copy, written to profiles/traffic.json
-with the hash of the stepper's kernel sources (readers ignore entries taken
-on other sources) and printed as a table;
+the same counters read for the 1 GiB copy, merged into profiles/traffic.json
+under keys naming the kernel and the grid, with the hash of the stepper's
+kernel sources (readers ignore entries taken on other sources), and printed
+as a table;
 
     python3 -m paper_1901_06535_amd.profile_kernels --stats KERNEL_STATS.csv
 
@@ -43,7 +46,7 @@ import numpy as np
 from . import inputs, rdc
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STEPPER_SOURCES = ("cell.h", "tile.h", "kernels.h", "kernels.hip")
+STEPPER_SOURCES = ("cell.h", "tile.h", "kernels.h", "kernels.hip", "stream.hip", "tiles_impl.h")
 
 
 def source_hash() -> str:
@@ -66,6 +69,9 @@ def _short(name: str) -> str:
     if m:
         return "k_stepT<T=%s,rows=%d%s>" % (m.group(1), 8 * int(m.group(2)),
                                            ",arrival" if m.group(3) == "true" else "")
+    m = re.match(r"k_stream<(\d+)>", n)
+    if m:
+        return "k_stream<T=%s>" % m.group(1)
     m = re.match(r"k_step1<(\w+), (\w+)>", n)
     if m:
         return "k_step1<%s%s>" % (m.group(1), ",arrival" if m.group(2) == "true" else "")
@@ -98,7 +104,7 @@ def valu(path: str, cus: int = 256, xcds: int = 8) -> None:
     SQ_INSTS_VALU / (GRBM_GUI_ACTIVE / xcds * cus) (4 SIMDs x 1/4)."""
     m = {c: _counter_means(path, c) for c in VALU_COUNTERS}
     for k in sorted(m["SQ_INSTS_VALU"]):
-        if not k.startswith("k_step") and k != "k_copy16":
+        if not k.startswith("k_st") and k != "k_copy16":
             continue
         g = lambda c: m[c].get(k, (float("nan"), 0))[0]
         gui = g("GRBM_GUI_ACTIVE")
@@ -108,46 +114,75 @@ def valu(path: str, cus: int = 256, xcds: int = 8) -> None:
                  g("SQ_INSTS_LDS"), 100 * busy))
 
 
-def summarize(fetch_csv: str, write_csv: str, out_json: str) -> None:
+GRIDS = {"uniform": 16384, "circuit": 4096}
+
+
+def traffic_key(kernel: str, grid: int):
+    """profiles/traffic.json key of a kernel (short name) on an n x n grid."""
+    m = re.match(r"k_stepT<T=(\d+),rows=(\d+)>$", kernel)
+    if m:
+        return "stepT_T%s_r%s_%dx%d" % (m.group(1), m.group(2), grid, grid)
+    m = re.match(r"k_stream<T=(\d+)>$", kernel)
+    if m:
+        return "stream_T%s_%dx%d" % (m.group(1), grid, grid)
+    m = re.match(r"k_stepT64<T=(\d+),rows=(\d+)>$", kernel)
+    if m:
+        return "stepT64_T%s_r%s_%dx%d" % (m.group(1), m.group(2), grid, grid)
+    base = {"k_step1<float>": "step1", "k_step1<double>": "step1_f64"}.get(kernel)
+    return "%s_%dx%d" % (base, grid, grid) if base else None
+
+
+def summarize(fetch_csv: str, write_csv: str, out_json: str, workload: str) -> None:
     f = _counter_means(fetch_csv, "FETCH_SIZE")
     w = _counter_means(write_csv, "WRITE_SIZE")
     gib_kib = (1 << 30) / 1024
     sf, sw = gib_kib / f["k_copy16"][0], gib_kib / w["k_copy16"][0]
-    rec = {"_note": "Per-launch HBM bytes of each kernel from rocprofv3 FETCH_SIZE and "
+    try:
+        with open(out_json) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        rec = {}
+    rec["_note"] = ("Per-launch HBM bytes of each kernel from rocprofv3 FETCH_SIZE and "
                     "WRITE_SIZE (KiB per dispatch), scaled by the readings of a 1 GiB copy "
                     "kernel; source_hash identifies the stepper sources the counters were "
-                    "taken on.",
-           "scale": {"fetch": round(sf, 4), "write": round(sw, 4)}}
+                    "taken on.")
+    rec.setdefault("scale", {})[workload] = {"fetch": round(sf, 4), "write": round(sw, 4)}
     print("scale FETCH x%.4f WRITE x%.4f (copy kernel, 1 GiB read + 1 GiB written)" % (sf, sw))
     h = source_hash()
     for k in sorted(f):
-        if k not in w or k == "k_copy16" or not k.startswith("k_step"):
+        if k not in w or k == "k_copy16" or not k.startswith("k_st"):
             continue
         rd, wr = f[k][0] * 1024 * sf, w[k][0] * 1024 * sw
-        m = re.match(r"k_stepT<T=(\d+),rows=(\d+)>$", k)
-        m64 = re.match(r"k_stepT64<T=(\d+),rows=(\d+)>$", k)
-        key = ("stepT_T%s_r%s_4096x4096" % m.groups()) if m else (
-            ("stepT64_T%s_r%s_16384x16384" % m64.groups()) if m64 else
-            {"k_step1<float>": "step1_16384x16384",
-             "k_step1<double>": "step1_f64_16384x16384"}.get(k))
+        key = traffic_key(k, GRIDS[workload])
         print("%-28s n=%2d fetch_KiB=%12.1f write_KiB=%12.1f -> read_MB=%9.1f written_MB=%9.1f"
               % (k, f[k][1], f[k][0], w[k][0], rd / 1e6, wr / 1e6))
         if key:
             rec[key] = {"kernel": k, "bytes_read": int(rd), "bytes_written": int(wr),
                         "bytes_per_launch": int(rd + wr), "source_hash": h}
     with open(out_json, "w") as fh:
-        json.dump(rec, fh, indent=1)
+        json.dump(rec, fh, indent=1, sort_keys=True)
 
-CANDIDATES = [(T, r) for T in (4, 6, 8, 9, 10, 11, 12) for r in (48, 56, 64, 80)]
+
+TILE_CANDIDATES = [(T, r) for T in (4, 6, 8, 9, 10, 11, 12) for r in (48, 56, 64, 80)]
+STREAM_CANDIDATES = (4, 6, 7, 8, 9)
+UNIFORM_TILES = [(8, 56), (8, 64), (10, 64), (11, 64), (12, 64)]
 CANDIDATES64 = [(8, 56), (8, 64)]
 LAUNCHES = 4
+
+
+def _launch_all(sim, shapes, log, grid):
+    for T, rows in shapes:
+        sim.set_block(T)
+        sim.set_tile_rows(rows)
+        sim.step(LAUNCHES * T)
+        name = ("k_stream<T=%d>" % T) if rows == 1 else ("k_stepT<T=%d,rows=%d>" % (T, rows))
+        log.append({"kernel": name, "grid": grid, "launches": LAUNCHES})
 
 
 def main():
     import torch
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--big", type=int, default=16384)
+    ap.add_argument("--workload", default="uniform", choices=sorted(GRIDS))
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--stats", metavar="KERNEL_STATS_CSV")
     ap.add_argument("--valu", metavar="COUNTER_CSV")
@@ -156,50 +191,48 @@ def main():
                                                   "traffic.json"))
     args = ap.parse_args()
     if args.summarize:
-        return summarize(args.summarize[0], args.summarize[1], args.out)
+        return summarize(args.summarize[0], args.summarize[1], args.out, args.workload)
     if args.stats:
         return stats(args.stats, args.top)
     if args.valu:
         return valu(args.valu)
     log = []
-    wl = inputs.circuit(n=args.n, seed=1002, steps=10000, ndisks=256)
+    n = GRIDS[args.workload]
+    if args.workload == "circuit":
+        wl = inputs.circuit(n=n, seed=1002, steps=10000, ndisks=256)
+    else:
+        wl = inputs.uniform_random_phi(n=n, seed=1003, steps=2000)
     sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
     sim.set_phi(wl.phi)
     sim.write(wl.u0, wl.v0)
     sim.stimulate([(s.cx, s.cy, s.r) for s in wl.stimuli[:32]])
-    for T, rows in CANDIDATES:
-        sim.set_block(T)
-        sim.set_tile_rows(rows)
-        sim.step(LAUNCHES * T)
-        log.append({"kernel": "k_stepT<T=%d,rows=%d>" % (T, rows), "grid": [wl.nx, wl.ny],
-                    "launches": LAUNCHES})
+    grid = [wl.nx, wl.ny]
+    stream = [(T, 1) for T in STREAM_CANDIDATES]
+    if args.workload == "circuit":
+        _launch_all(sim, stream + TILE_CANDIDATES, log, grid)
+    else:
+        _launch_all(sim, stream + UNIFORM_TILES, log, grid)
+        sim.set_block(1)
+        sim.step(LAUNCHES)
+        log.append({"kernel": "k_step1<float>", "grid": grid, "launches": LAUNCHES})
     sim.synchronize()
     sim.close()
 
-    n = args.big
-    big = rdc.Sim(n, n, inputs.PARAMS_WORKLOAD, "fp32")
-    rng = np.random.default_rng(1003)
-    big.set_phi((0.04 + 0.04 * rng.random((n, n), dtype=np.float32)).astype(np.float32))
-    big.set_block(1)
-    big.step(LAUNCHES)
-    big.synchronize()
-    log.append({"kernel": "k_step1<float>", "grid": [n, n], "launches": LAUNCHES})
-    big.close()
-
-    # FP64 on the same grid: the one-step kernel and the T-step kernel.
-    b64 = rdc.Sim(n, n, inputs.PARAMS_WORKLOAD, "fp64")
-    b64.set_phi((0.04 + 0.04 * rng.random((n, n))).astype(np.float64))
-    b64.set_block(1)
-    b64.step(LAUNCHES)
-    log.append({"kernel": "k_step1<double>", "grid": [n, n], "launches": LAUNCHES})
-    for T, rows in CANDIDATES64:
-        b64.set_block(T)
-        b64.set_tile_rows(rows)
-        b64.step(LAUNCHES * T)
-        log.append({"kernel": "k_stepT64<T=%d,rows=%d>" % (T, rows), "grid": [n, n],
-                    "launches": LAUNCHES})
-    b64.synchronize()
-    b64.close()
+    if args.workload == "uniform":
+        # FP64 on the same grid: the one-step kernel and the T-step kernel.
+        b64 = rdc.Sim(n, n, wl.params, "fp64")
+        b64.set_phi(wl.phi.astype(np.float64))
+        b64.set_block(1)
+        b64.step(LAUNCHES)
+        log.append({"kernel": "k_step1<double>", "grid": grid, "launches": LAUNCHES})
+        for T, rows in CANDIDATES64:
+            b64.set_block(T)
+            b64.set_tile_rows(rows)
+            b64.step(LAUNCHES * T)
+            log.append({"kernel": "k_stepT64<T=%d,rows=%d>" % (T, rows), "grid": grid,
+                        "launches": LAUNCHES})
+        b64.synchronize()
+        b64.close()
 
     nb = 1 << 30
     src = torch.zeros(nb // 4, dtype=torch.float32, device="cuda")

@@ -23,6 +23,9 @@ RDC_OK, RDC_E_INVAL, RDC_E_NOMEM, RDC_E_DEVICE, RDC_E_NONFINITE, RDC_E_STATE = 0
 RDC_FP32, RDC_FP64 = 0, 1
 RDC_HOST, RDC_DEVICE = 0, 1
 NEVER = 0x7FFFFFFF
+# rdc_set_tile_rows value for the row-pipeline kernel (register-resident
+# strips instead of LDS tiles)
+RDC_TILE_STREAM = 1
 
 # Every symbol include/rdc.h declares.
 EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_write",

@@ -70,3 +70,14 @@ def front_error(a: np.ndarray, b: np.ndarray, theta: float = 0.5, kmax: int = 64
             return k
         da, db = dilate(da, 1), dilate(db, 1)
     return kmax + 1
+
+
+def background_far_from_channels(phi: np.ndarray, d: int = 4, phi_bg: float = 0.2) -> np.ndarray:
+    """Cells of the phi = phi_bg background at Chebyshev distance >= d from
+    any other cell.  On the phi = 0.2 background the homogeneous state is on
+    a period-2 orbit of the cell map; waves in the channels perturb cells
+    this far away by less than 1e-4 (the FP64 oracle's state there is within
+    4e-5 of the homogeneous orbit at d = 4 on the 512^2 circuit)."""
+    from scipy.ndimage import distance_transform_cdt
+    bg = phi == np.float32(phi_bg)
+    return bg & (distance_transform_cdt(bg, metric="chessboard") >= d)

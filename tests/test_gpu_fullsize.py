@@ -8,12 +8,16 @@ domain corners and edges).  Here the GPU runs the same seeded workload:
   * FP64 kernel: u, v and arrival time bit-identical at every sample;
   * FP32, the launch shapes the benchmark's tuner picks from (8 to 12 steps
     per launch; 56- and 64-row tiles): arrival within one cell both ways, and max-abs <= 1e-4 on the
-    samples outside the one-cell dilation of the oracle's Euler-unstable set.
+    samples outside the one-cell dilation of the oracle's Euler-unstable set;
+  * FP32 row pipelines (which take no arrival map): the whole final field
+    bit-identical to the tile kernel's.
 """
 import os
 
 import numpy as np
 import pytest
+
+from metrics import background_far_from_channels
 
 from paper_1901_06535_amd import inputs, rdc
 
@@ -106,3 +110,80 @@ def test_fp32_bench_launch_shape_at_samples(case, T, rows):
     assert ok_gpu.all() and ok_ref.all()
     assert arrived > 1000
     assert du <= TOL and dv <= TOL
+    if name == "circuit_4096":
+        # sampled cells of the phi = 0.2 background away from the channels:
+        # the period-2 orbit, the same phase in both precisions
+        p2 = background_far_from_channels(wl.phi)[ref["idx"][:, 0], ref["idx"][:, 1]]
+        du2 = float(np.abs(u - ref["u"])[p2].max())
+        dv2 = float(np.abs(v - ref["v"])[p2].max())
+        print("  period-2 background samples %d: max|du| %.3g max|dv| %.3g"
+              % (int(p2.sum()), du2, dv2))
+        assert p2.sum() > 1000
+        assert du2 <= TOL and dv2 <= TOL
+
+
+def _oracle_arrival(ref, ny, nx):
+    hit = np.unpackbits(ref["arr_bits"], count=ny * nx).astype(bool).reshape(ny, nx)
+    arr = np.full((ny, nx), np.iinfo(np.int32).max, dtype=np.int64)
+    arr[hit] = ref["arr_vals"]
+    return arr
+
+
+def _neigh_minmax_gpu(torch, a):
+    """Min and max over each cell's 3x3 neighbourhood (edge cells repeat the
+    edge), on the GPU; arrival times as float64 (exact)."""
+    t = a.to(torch.float64)[None, None]
+    p = torch.nn.functional.pad(t, (1, 1, 1, 1), mode="replicate")
+    hi = torch.nn.functional.max_pool2d(p, 3, stride=1)[0, 0]
+    lo = -torch.nn.functional.max_pool2d(-p, 3, stride=1)[0, 0]
+    return lo, hi
+
+
+@pytest.mark.parametrize("dtype,T,rows", [("fp64", 8, 56), ("fp32", 8, 64), ("fp32", 11, 64)])
+def test_circuit_arrival_over_the_whole_field(dtype, T, rows):
+    """The 4096^2 circuit run's arrival map (first step with u >= 0.5) in
+    every cell against the oracle's whole map: FP64 identical, FP32 within
+    one cell both ways."""
+    import torch
+    ref = _load("circuit_4096")
+    wl = _workload("circuit_4096")
+    assert str(ref["manifest"]) == wl.manifest_json(), "golden file is for another workload"
+    print("[case] whole-field arrival %s T=%d rows=%d" % (dtype, T, rows), flush=True)
+    oracle_arr = _oracle_arrival(ref, wl.ny, wl.nx)
+    s, _ = _run(wl, dtype, T=T, rows=rows)
+    gpu = s.arrival_plane[:, : s.nx].to(torch.int64)
+    s.close()
+    ref_t = torch.as_tensor(oracle_arr, device=gpu.device)
+    if dtype == "fp64":
+        assert torch.equal(gpu, ref_t)
+        return
+    lo, hi = _neigh_minmax_gpu(torch, ref_t)
+    g = gpu.to(torch.float64)
+    bad_gpu = int(((g < lo) | (g > hi)).sum())
+    lo2, hi2 = _neigh_minmax_gpu(torch, gpu)
+    r = ref_t.to(torch.float64)
+    bad_ref = int(((r < lo2) | (r > hi2)).sum())
+    arrived = int((ref_t < np.iinfo(np.int32).max).sum())
+    print("  arrived %d of %d cells; violations %d / %d" % (arrived, wl.nx * wl.ny, bad_gpu,
+                                                          bad_ref))
+    assert arrived > 500000
+    assert bad_gpu == 0 and bad_ref == 0
+
+
+@pytest.mark.parametrize("T", [8, 9])
+def test_fp32_row_pipelines_equal_tiles_over_the_whole_field(case, T):
+    name, wl, ref = case
+    print("[case] fp32 row pipelines %s T=%d" % (name, T), flush=True)
+    out = []
+    for t, rows in ((8, 64), (T, rdc.RDC_TILE_STREAM)):
+        s = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
+        s.set_phi(wl.phi)
+        s.write(wl.u0, wl.v0)
+        s.set_block(t)
+        s.set_tile_rows(rows)
+        s.run_schedule(wl.stimuli, wl.steps)
+        u, v = s.current()
+        out.append((u.clone(), v.clone()))
+        s.close()
+    import torch
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])

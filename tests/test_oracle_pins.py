@@ -337,6 +337,57 @@ def test_inhibitory_background_settles_on_period_two_orbit():
     assert min(seq) < us < max(seq)
 
 
+def _cell_map(params, phi, u, v):
+    """One forward-Euler step of Eq. (1) for a cell of a homogeneous field
+    (the five-node Laplacian of a constant is zero), written out here."""
+    q = params["q"]
+    react = (u - u * u - (params["f"] * v + phi) * (u - q) / (u + q)) / params["eps"]
+    return u + params["dt"] * react, v + params["dt"] * (u - v)
+
+
+def _two_cycle_newton(params, phi, guess):
+    """A period-2 point of the cell map: Newton's method on F(F(x)) - x with
+    a central-difference Jacobian."""
+    def g(x):
+        return np.array(_cell_map(params, phi, *_cell_map(params, phi, *x))) - x
+    x = np.array(guess, dtype=np.float64)
+    for _ in range(60):
+        jac = np.empty((2, 2))
+        for j in range(2):
+            h = 1e-9 * max(1e-3, abs(x[j]))
+            e = np.zeros(2)
+            e[j] = h
+            jac[:, j] = (g(x + e) - g(x - e)) / (2 * h)
+        dx = np.linalg.solve(jac, -g(x))
+        x = x + dx
+        if np.abs(dx).max() < 1e-17:
+            break
+    return x
+
+
+@pytest.mark.parametrize("eps", [0.022, 0.02, 0.0243])
+def test_period_two_orbit_values_on_inhibitory_background(eps):
+    """The 2-cycle the oracle settles on from u = v = 0 on phi = 0.2 is the
+    one Newton's method finds for the cell map (to 1e-9 in u and v, with the
+    phase the run reaches), a true 2-cycle (not the fixed point), and it
+    meets the invariant the v-equation alone fixes: over one period v
+    changes by dt (u1 - v1) + dt (u2 - v2) = 0, so u1 + u2 = v1 + v2."""
+    p = dict(P, eps=eps)
+    x1 = _two_cycle_newton(p, 0.2, (0.0011, 0.00247))
+    x2 = np.array(_cell_map(p, 0.2, *x1))
+    assert np.abs(x1 - x2).max() > 1e-4                         # not the fixed point
+    assert abs((x1[0] + x2[0]) - (x1[1] + x2[1])) < 1e-15
+    run = oracle.Run(np.zeros((2, 2)), np.zeros((2, 2)), np.full((2, 2), 0.2), p)
+    run.advance(25000)
+    a = np.array([run.u[0, 0], run.v[0, 0]])
+    run.advance(1)
+    b = np.array([run.u[0, 0], run.v[0, 0]])
+    if np.abs(a - x1).max() > np.abs(a - x2).max():
+        a, b = b, a
+    assert np.abs(a - x1).max() < 1e-9 and np.abs(b - x2).max() < 1e-9
+    assert abs((a[0] + b[0]) - (a[1] + b[1])) < 1e-12
+
+
 # ---------------------------------------------------------------- timelapse
 
 @pytest.mark.parametrize("rate,chunks", [(1, [7, 5]), (3, [1, 1, 10, 4]), (7, [20, 2])])

@@ -84,3 +84,29 @@ def test_pool_and_upsample_conventions():
     assert p[0, 0, 0, 0] == (0 + 1 + 4 + 5) / 4
     u = torch.nn.functional.interpolate(p, scale_factor=2, mode="nearest")
     assert u[0, 0, 1, 1] == p[0, 0, 0, 0] and u[0, 0, 2, 3] == p[0, 0, 1, 1]
+
+
+def test_loss_on_a_hand_computed_two_pixel_case():
+    """loss on one image of 1 x 2 pixels, worked by hand: su = 2, sv = 8,
+    theta = 0.5, front weight 4.
+      pixel 0: u 0.2 -> ut 0.6 crosses theta: weight 5; targets su*0.4 =
+               0.8, sv*0.2 = 1.6; head (0.5, 1.0): 5 * (0.09 + 0.36) = 2.25
+      pixel 1: u 0.7 -> ut 0.7 stays above: weight 1; targets 0, sv*0.05 =
+               0.4; head (0.1, 0.4): 1 * (0.01 + 0) = 0.01
+      mean over the two pixels: 1.13"""
+    head = torch.zeros((1, 1, 2, 32), dtype=torch.float64)
+    head[0, 0, 0, 0], head[0, 0, 0, 1] = 0.5, 1.0
+    head[0, 0, 1, 0], head[0, 0, 1, 1] = 0.1, 0.4
+    head[0, 0, :, 2:] = 7.0                   # channels past the first two play no part
+    u = np.array([[[0.2, 0.7]]])
+    ut = np.array([[[0.6, 0.7]]])
+    v = np.array([[[0.1, 0.0]]])
+    vt = np.array([[[0.3, 0.05]]])
+    L = unet_ref.loss(head, u, v, ut, vt, su=2.0, sv=8.0, theta=0.5, front_w=4.0)
+    assert abs(float(L) - 1.13) < 1e-12
+    # both cells above or both below theta: no front weight
+    L2 = unet_ref.loss(head, u, v, np.array([[[0.3, 0.9]]]), vt, su=2.0, sv=8.0, theta=0.5,
+                       front_w=4.0)
+    e0 = (0.5 - 2.0 * 0.1) ** 2 + (1.0 - 8.0 * 0.2) ** 2
+    e1 = (0.1 - 2.0 * 0.2) ** 2 + (0.4 - 8.0 * 0.05) ** 2
+    assert abs(float(L2) - (e0 + e1) / 2) < 1e-12
