@@ -409,9 +409,10 @@ def apply(net: UNet, ws: Workspace, u, v, phi, uo, vo, pitch, plane_stride, para
 
 def training_batch_sims(n: int, count: int, seed: int, steps: int) -> List[inputs.Workload]:
     """Random circuit maps (channels on phi=0.2, diodes and AND junctions)
-    with input disks spread over the first `steps` steps."""
+    with input disks over the first `steps` steps, the earliest candidates
+    kept first (waves are under way once the burn-in ends)."""
     return [inputs.circuit(n=n, seed=seed + i, steps=steps, ndisks=max(4, (n // 128) ** 2),
-                           tile=128) for i in range(count)]
+                           tile=128, disk_order="time") for i in range(count)]
 
 
 class Trainer:

@@ -38,7 +38,7 @@ def _plain_run(wl, until):
 
 
 def _workload(seed=7, n=256, steps=1500):
-    return inputs.circuit(n=n, seed=seed, steps=steps, ndisks=4, tile=128)
+    return inputs.circuit(n=n, seed=seed, steps=steps, ndisks=4, tile=128, disk_order="time")
 
 
 def test_training_lowers_the_loss(trained):
