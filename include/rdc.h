@@ -376,6 +376,26 @@ rdc_status rdc_nn_conv3x3_wgrad(const void *x, int32_t ldx, const void *dy, int3
                                 float *scratch, float *grad, float *gbias, int32_t n, int32_t h,
                                 int32_t w, int32_t cin, int32_t cout, void *stream);
 
+/* rdc_nn_conv3x3_wgrad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid allocation): the same kernels and results, with the partials in a
+ * static device array of the library instead of a caller's `scratch` (one
+ * array per GPU, rdc_nn_wgrad_static_floats() floats = 32 MiB, held until
+ * the process ends).  Allocates nothing and needs no clearing (every partial
+ * a call sums is written by that call first).  Calls on one GPU share the
+ * array: calls that overlap in time there (e.g. on two streams) race and give
+ * wrong gradients; calls queued on one stream are ordered and safe.
+ * Errors: as rdc_nn_conv3x3_wgrad, plus RDC_E_INVAL when the shape needs
+ * more than rdc_nn_wgrad_static_floats() floats of workspace
+ * (rdc_nn_wgrad_scratch_floats), RDC_E_DEVICE if the array's address cannot
+ * be had. */
+rdc_status rdc_nn_conv3x3_wgrad_noalloc(const void *x, int32_t ldx, const void *dy, int32_t lddy,
+                                        float *grad, float *gbias, int32_t n, int32_t h,
+                                        int32_t w, int32_t cin, int32_t cout, void *stream);
+
+/* Floats of workspace the static scratch of rdc_nn_conv3x3_wgrad_noalloc holds. */
+int64_t rdc_nn_wgrad_static_floats(void);
+
 /* dst = bf16(src), n elements. */
 rdc_status rdc_nn_to_bf16(const float *src, void *dst, int64_t n, void *stream);
 

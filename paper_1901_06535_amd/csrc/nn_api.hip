@@ -1,24 +1,59 @@
 // nn_api.hip -- C ABI (include/rdc.h, rdc_nn_*) of the learned coarse
 // stepper's kernels: argument checks and launches on the caller's stream.
 #include <cstdint>
-#include <string>
+#include <cstdio>
+#include <mutex>
 
 #include "../../include/rdc.h"
 #include "nn.h"
 
+// Workspace of rdc_nn_conv3x3_wgrad_noalloc, for callers that cannot
+// allocate: one copy per GPU, held until the process ends.
+constexpr int64_t kStaticScratchFloats = int64_t(8) << 20;   // 32 MiB
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
 namespace {
 
-thread_local std::string g_nn_error;
+// The last error of this thread, in a fixed buffer (no heap use on any path).
+thread_local char g_nn_error[256];
 
 rdc_status nfail(const char* m) {
-    g_nn_error = m;
+    std::snprintf(g_nn_error, sizeof g_nn_error, "%s", m);
     return RDC_E_INVAL;
 }
 
 rdc_status nhip(hipError_t e) {
     if (e == hipSuccess) return RDC_OK;
-    g_nn_error = std::string("launch: ") + hipGetErrorString(e);
+    std::snprintf(g_nn_error, sizeof g_nn_error, "launch: %s", hipGetErrorString(e));
     return RDC_E_DEVICE;
+}
+
+// Device address of `scratch` on the current device.  In host code the
+// array's name stands for no device address, so every use goes through the
+// address hipGetSymbolAddress gives, taken once per device (each GPU holds
+// its own copy at its own address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+rdc_status static_scratch(float** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return nhip(e);
+    if (dev < 0 || dev >= kMaxDevices) return nfail("device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            std::snprintf(g_nn_error, sizeof g_nn_error, "static scratch address: %s",
+                          hipGetErrorString(e));
+            return RDC_E_DEVICE;
+        }
+        g_scratch_dev[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return RDC_OK;
 }
 
 bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -29,7 +64,7 @@ hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
 
 extern "C" {
 
-const char* rdc_nn_last_error(void) { return g_nn_error.c_str(); }
+const char* rdc_nn_last_error(void) { return g_nn_error; }
 
 rdc_status rdc_nn_conv3x3(const void* x, int32_t ldx, const void* w, const float* bias, void* y,
                           int32_t ldy, int32_t n, int32_t h, int32_t wd, int32_t cin,
@@ -185,19 +220,29 @@ int64_t rdc_nn_wgrad_scratch_floats(int32_t n, int32_t h, int32_t w, int32_t cin
     return rdc::nn::wgrad_chunks(n, h, w) * (9 * (int64_t)cout * cin + cout);
 }
 
-rdc_status rdc_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_t lddy,
-                                float* scratch, float* grad, float* gbias, int32_t n, int32_t h,
-                                int32_t w, int32_t cin, int32_t cout, void* stream) {
-    if (!x || !dy || !scratch || !grad) return nfail("NULL tensor");
+}  // extern "C"
+
+namespace {
+
+// Checks of the weight-gradient calls; the partials go to `work`.
+rdc_status wgrad_args(const void* x, int32_t ldx, const void* dy, int32_t lddy, const float* grad,
+                      int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout) {
+    if (!x || !dy || !grad) return nfail("NULL tensor");
     if (n < 1 || h < 1 || w < 32 || w % 32) return nfail("need w a multiple of 32");
     if (cin < 32 || cin % 32 || cout < 32 || cout % 32) return nfail("need cin, cout % 32 == 0");
     if (ldx < cin || ldx % 8 || lddy < cout || lddy % 8) return nfail("bad strides");
     if (!al16(x) || !al16(dy)) return nfail("x, dy need 16-byte alignment");
+    return RDC_OK;
+}
+
+rdc_status wgrad_launch(const void* x, int32_t ldx, const void* dy, int32_t lddy, float* work,
+                        float* grad, float* gbias, int32_t n, int32_t h, int32_t w, int32_t cin,
+                        int32_t cout, void* stream) {
     rdc::nn::WgradArgs a;
     a.x = static_cast<const __bf16*>(x);
     a.dy = static_cast<const __bf16*>(dy);
-    a.part = scratch;
-    a.bpart = gbias ? scratch + rdc::nn::wgrad_chunks(n, h, w) * 9 * (int64_t)cout * cin : nullptr;
+    a.part = work;
+    a.bpart = gbias ? work + rdc::nn::wgrad_chunks(n, h, w) * 9 * (int64_t)cout * cin : nullptr;
     a.ldx = ldx;
     a.lddy = lddy;
     a.N = n;
@@ -206,6 +251,34 @@ rdc_status rdc_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int3
     a.cin = cin;
     a.cout = cout;
     return nhip(rdc::nn::conv3x3_wgrad(a, grad, gbias, S(stream)));
+}
+
+}  // namespace
+
+extern "C" {
+
+rdc_status rdc_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_t lddy,
+                                float* scratch_arg, float* grad, float* gbias, int32_t n, int32_t h,
+                                int32_t w, int32_t cin, int32_t cout, void* stream) {
+    if (!scratch_arg) return nfail("NULL tensor");
+    if (rdc_status st = wgrad_args(x, ldx, dy, lddy, grad, n, h, w, cin, cout)) return st;
+    return wgrad_launch(x, ldx, dy, lddy, scratch_arg, grad, gbias, n, h, w, cin, cout, stream);
+}
+
+int64_t rdc_nn_wgrad_static_floats(void) { return kStaticScratchFloats; }
+
+rdc_status rdc_nn_conv3x3_wgrad_noalloc(const void* x, int32_t ldx, const void* dy, int32_t lddy,
+                                        float* grad, float* gbias, int32_t n, int32_t h,
+                                        int32_t w, int32_t cin, int32_t cout, void* stream) {
+    if (rdc_status st = wgrad_args(x, ldx, dy, lddy, grad, n, h, w, cin, cout)) return st;
+    if (rdc_nn_wgrad_scratch_floats(n, h, w, cin, cout) > kStaticScratchFloats)
+        return nfail("shape needs more workspace than the static scratch holds "
+                     "(rdc_nn_wgrad_scratch_floats > rdc_nn_wgrad_static_floats)");
+    float* work = nullptr;
+    if (rdc_status st = static_scratch(&work)) return st;
+    // Every partial the summing launches read is written first by the
+    // partial launch of the same call, so the scratch needs no clearing.
+    return wgrad_launch(x, ldx, dy, lddy, work, grad, gbias, n, h, w, cin, cout, stream);
 }
 
 rdc_status rdc_nn_to_bf16(const float* src, void* dst, int64_t n, void* stream) {

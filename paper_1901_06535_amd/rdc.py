@@ -39,7 +39,8 @@ EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_wr
            "rdc_nn_conv3x3", "rdc_nn_conv3x3_up", "rdc_nn_conv3x3_planes",
            "rdc_nn_conv3x3_apply",
            "rdc_nn_dgrad_weights", "rdc_nn_wgrad_scratch_floats",
-           "rdc_nn_conv3x3_wgrad", "rdc_nn_to_bf16", "rdc_nn_relu_bwd",
+           "rdc_nn_conv3x3_wgrad", "rdc_nn_conv3x3_wgrad_noalloc", "rdc_nn_wgrad_static_floats",
+           "rdc_nn_to_bf16", "rdc_nn_relu_bwd",
            "rdc_nn_pool2", "rdc_nn_pool2_bwd", "rdc_nn_up2", "rdc_nn_up2_bwd", "rdc_nn_prep",
            "rdc_nn_apply", "rdc_nn_loss_blocks", "rdc_nn_loss", "rdc_nn_adam",
            "rdc_nn_front_check", "rdc_nn_state_check", "rdc_nn_last_error")
@@ -127,6 +128,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "rdc_nn_dgrad_weights": (i32, [vp, vp, i32, i32, vp]),
         "rdc_nn_wgrad_scratch_floats": (i64, [i32, i32, i32, i32, i32]),
         "rdc_nn_conv3x3_wgrad": (i32, [vp, i32, vp, i32, vp, vp, vp, i32, i32, i32, i32, i32, vp]),
+        "rdc_nn_conv3x3_wgrad_noalloc": (i32, [vp, i32, vp, i32, vp, vp, i32, i32, i32, i32, i32,
+                                               vp]),
+        "rdc_nn_wgrad_static_floats": (i64, []),
         "rdc_nn_to_bf16": (i32, [vp, vp, i64, vp]),
         "rdc_nn_relu_bwd": (i32, [vp, i32, vp, i32, i64, i32, vp]),
         "rdc_nn_pool2": (i32, [vp, i32, vp, i32, i32, i32, i32, i32, vp]),

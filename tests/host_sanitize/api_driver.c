@@ -284,6 +284,18 @@ static void nn(void) {
            RDC_OK);
     EXPECT(rdc_nn_conv3x3_wgrad(x, cin, y, cout, scratch, grad, gb, n, h, w, 16, cout, NULL) ==
            RDC_E_INVAL);
+    /* the variant that allocates nothing: same launches, static workspace */
+    const long live = shim_live_allocations();
+    EXPECT(rdc_nn_conv3x3_wgrad_noalloc(x, cin, y, cout, grad, gb, n, h, w, cin, cout, NULL) ==
+           RDC_OK);
+    EXPECT(rdc_nn_conv3x3_wgrad_noalloc(x, cin, y, cout, grad, NULL, n, h, w, cin, cout, NULL) ==
+           RDC_OK);
+    EXPECT(shim_live_allocations() == live);
+    EXPECT(rdc_nn_conv3x3_wgrad_noalloc(x, cin, y, cout, grad, gb, n, h, w, 16, cout, NULL) ==
+           RDC_E_INVAL);
+    EXPECT(rdc_nn_wgrad_scratch_floats(16, 512, 512, 32, 32) > rdc_nn_wgrad_static_floats());
+    EXPECT(rdc_nn_conv3x3_wgrad_noalloc(x, cin, y, cout, grad, gb, 16, 512, 512, 32, 32, NULL) ==
+           RDC_E_INVAL);
     EXPECT(rdc_nn_to_bf16(wf, wt, 9 * cin * cout, NULL) == RDC_OK);
     EXPECT(rdc_nn_relu_bwd(y, cout, y, cout, px, cout, NULL) == RDC_OK);
     void *lo = dev(px * cin * 2 / 4);

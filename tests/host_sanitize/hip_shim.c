@@ -120,3 +120,13 @@ void __hipRegisterFunction(void **m, const void *h, char *d, const char *n, unsi
     (void)m; (void)h; (void)d; (void)n; (void)t; (void)a; (void)b; (void)c; (void)e; (void)w;
 }
 void __hipUnregisterFatBinary(void **m) { (void)m; }
+/* A __device__ variable: its host shadow stands in for the device copy. */
+void __hipRegisterVar(void **m, void *var, char *host_var, char *dev_var, int ext, size_t size,
+                      int constant, int global) {
+    (void)m; (void)var; (void)host_var; (void)dev_var; (void)ext; (void)size; (void)constant;
+    (void)global;
+}
+hipError_t hipGetSymbolAddress(void **p, const void *symbol) {
+    *p = (void *)symbol;
+    return ok;
+}

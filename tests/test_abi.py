@@ -159,6 +159,17 @@ def test_nn_argument_checks(lib):
     assert lib.rdc_nn_conv3x3_wgrad(FAKE, 32, FAKE, 32, FAKE, FAKE, None, 1, 4, 64, 16, 32,
                                     None) == rdc.RDC_E_INVAL
     assert "% 32" in _nn_err(lib)
+    # the variant that allocates nothing: the same checks, and shapes whose
+    # workspace exceeds its static scratch are refused before any device call
+    assert lib.rdc_nn_conv3x3_wgrad_noalloc(FAKE, 32, FAKE, 32, FAKE, None, 1, 4, 64, 16, 32,
+                                            None) == rdc.RDC_E_INVAL
+    assert "% 32" in _nn_err(lib)
+    cap = lib.rdc_nn_wgrad_static_floats()
+    assert cap == 8 << 20
+    assert lib.rdc_nn_wgrad_scratch_floats(16, 512, 512, 32, 32) > cap
+    assert lib.rdc_nn_conv3x3_wgrad_noalloc(FAKE, 32, FAKE, 32, FAKE, FAKE, 16, 512, 512, 32, 32,
+                                            None) == rdc.RDC_E_INVAL
+    assert "static scratch" in _nn_err(lib)
     # scratch size is zero for shapes the kernel rejects
     assert lib.rdc_nn_wgrad_scratch_floats(1, 4, 16, 32, 32) == 0
     assert lib.rdc_nn_wgrad_scratch_floats(1, 4, 64, 32, 32) > 0
