@@ -25,7 +25,7 @@ DEFAULT_T = (4, 6, 8, 9, 10, 11, 12)
 # LDS tile heights, and 1 = the row-pipeline kernel (rdc.RDC_TILE_STREAM)
 DEFAULT_ROWS = (48, 56, 64, 80, 1)
 # Most steps per launch the row-pipeline kernel takes (FP32 only).
-MAX_T_STREAM = 9
+MAX_T_STREAM = 11
 # Most steps per launch the library's tile kernels take, per precision
 # (rdc_set_block; the batched kernels are FP32).
 MAX_T = {"fp32": 12, "fp64": 8}

@@ -58,7 +58,7 @@ int tile_rows_default();
 // T forward-Euler steps per launch by register-resident row pipelines
 // (FP32, one wave per 256-column strip and segment of rows; no LDS tiles).
 // T in 2..kMaxStream; results bit-identical to launch_step1 and launch_stepT.
-constexpr int kMaxStream = 9;
+constexpr int kMaxStream = 11;
 struct StreamGeom {
     int bx;        // output columns per strip (a multiple of 4)
     int nstrips;   // strips across the grid

@@ -41,19 +41,11 @@ using namespace dev;
 
 constexpr int kStreamWaves = 4;   // waves per workgroup (independent pipelines)
 constexpr int kUnroll = 12;       // ticks per unrolled loop body
-constexpr int kRowSlots = 12;     // v, c1*phi rows held: row index mod 12
+constexpr int kRowSlots = 12;     // v of the rows in the levels: row index mod 12
 constexpr int kU0Slots = 6;       // u^0 rows held by level 1: row index mod 6
-// A row is loaded this many ticks before its first use (at most 3: the u^0
-// slots hold rows i-1 .. i+1+kAhead); fewer when T is large, so that the
-// row slots still hold every row in flight.  RDC_STREAM_AHEAD caps it (a
-// build-time tunable).
-#ifndef RDC_STREAM_AHEAD
-#define RDC_STREAM_AHEAD 3
-#endif
-template <int T>
-constexpr int stream_ahead() {
-    return (kRowSlots - 1 - T) < RDC_STREAM_AHEAD ? (kRowSlots - 1 - T) : RDC_STREAM_AHEAD;
-}
+constexpr int kAhead = 2;         // a row is loaded this many ticks before it enters level 1
+constexpr int kStage = 3;         // v, phi of loaded rows waiting to enter: row index mod 3
+constexpr int kPhiRows = 16;      // c1*phi rows in LDS per wave: row index mod 16
 // A buffer offset past any row (rows are shorter than 2 GiB): the access is
 // dropped.
 constexpr int kOff = static_cast<int>(0x80000000u);
@@ -65,12 +57,14 @@ constexpr int md(int a, int m) { return ((a % m) + m) % m; }
 template <int T>
 constexpr int stream_hx() { return (T + 3) & ~3; }
 
-// v and c1*phi of a row stay in their slot from the load until the last
-// level is done with the row: the slot is reloaded kRowSlots - 1 - kAhead
-// ticks after the row's first use.
+// Row slots: a row's v sits in its slot from the tick it enters level 1 to
+// the tick level T is done with it (T rows at a time); u^0 rows i-1 ..
+// i+1+kAhead fit the level-1 window; c1*phi rows in LDS likewise.
 template <int T>
 constexpr bool stream_fits() {
-    return T >= 2 && stream_ahead<T>() >= 1 && stream_ahead<T>() <= kU0Slots - 3;
+    return T >= 2 && T <= kRowSlots && T <= kPhiRows && kAhead + 3 <= kU0Slots &&
+           kAhead + 1 <= kStage && kUnroll % kRowSlots == 0 && kUnroll % kU0Slots == 0 &&
+           kUnroll % kStage == 0 && kUnroll % 3 == 0;
 }
 
 struct Lane {
@@ -83,9 +77,9 @@ struct Lane {
 
 template <int T, bool EDGE>
 __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const Lane& ln,
-                                                int y0, int y1) {
-    constexpr int kAhead = stream_ahead<T>();
+                                                int y0, int y1, float4 (&phs)[kPhiRows][64]) {
     const int ny = a.ny;
+    const int lane = threadIdx.x & 63;
     const int64_t P = a.pitch;
     const int row_bytes = static_cast<int>(P * 4);
     const int i0 = y0 - T + 1;                 // first tick: level 1 on row y0 - T + 1
@@ -102,8 +96,9 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
     // only where it ran on a row of the segment.  Slots start at zero.
     float u0[kU0Slots][4] = {};                // u^0 rows (level 1's window)
     float uw[T + 1][3][4] = {};                // uw[t]: rows of u^(t-1), t >= 2
-    float vr[kRowSlots][4] = {};               // v of rows in flight
-    float pr[kRowSlots][4] = {};               // c1*phi (raw phi until its first use)
+    float vr[kRowSlots][4] = {};               // v of the rows in the levels
+    float vs[kStage][4] = {};                  // v of loaded rows not yet in level 1
+    float ps[kStage][4] = {};                  // phi of loaded rows not yet in level 1
 
     // Load row r of u (and of v, phi); rows past the last one any level
     // needs (i_end) read nothing.
@@ -136,25 +131,31 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
     };
 
     // Rows the first ticks need: u^0 rows i0-1 .. i0+kAhead, v and phi rows
-    // i0 .. i0+kAhead (relative row j lives in slot j mod 6 / j mod 12).
-    load_row(i0 - 1, u0[md(-1, kU0Slots)], vr[md(-1, kRowSlots)], pr[md(-1, kRowSlots)], false);
+    // i0 .. i0+kAhead (relative row j: u^0 slot j mod 6, staging j mod 3).
+    load_row(i0 - 1, u0[md(-1, kU0Slots)], vs[md(-1, kStage)], ps[md(-1, kStage)], false);
 #pragma unroll
-    for (int j = 0; j <= kAhead; ++j) load_row(i0 + j, u0[j], vr[j], pr[j], true);
+    for (int j = 0; j <= kAhead; ++j)
+        load_row(i0 + j, u0[md(j, kU0Slots)], vs[md(j, kStage)], ps[md(j, kStage)], true);
 
     uint64_t bad = 0;
     for (int ib = i0; ib < i_end; ib += kUnroll) {
 #pragma unroll
         for (int s = 0; s < kUnroll; ++s) {
             const int i = ib + s;
-            // The row first needed kAhead ticks from now.  Its slots held row
-            // i + 1 + kAhead - 6 (u^0) and - 12 (v, phi), which every level
-            // has finished with.
-            load_row(i + 1 + kAhead, u0[md(s + 1 + kAhead, kU0Slots)],
-                     vr[md(s + 1 + kAhead, kRowSlots)], pr[md(s + 1 + kAhead, kRowSlots)], true);
-            // phi of row i enters level 1 now: scale it once.
+            // Row i enters level 1: its v moves to its row slot (which held
+            // row i - 12, done with since level T took it), its phi is
+            // scaled once and kept in the wave's LDS ring for the levels.
+            float cp[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                pr[md(s, kRowSlots)][c] = scaled_phi(pr[md(s, kRowSlots)][c], k);
+            for (int c = 0; c < 4; ++c) {
+                vr[md(s, kRowSlots)][c] = vs[md(s, kStage)][c];
+                cp[c] = scaled_phi(ps[md(s, kStage)][c], k);
+            }
+            phs[i & (kPhiRows - 1)][lane] = make_float4(cp[0], cp[1], cp[2], cp[3]);
+            // The row first needed kAhead ticks from now.  Its slots held row
+            // i + 1 + kAhead - 6 (u^0) and - 3 (staging), both done with.
+            load_row(i + 1 + kAhead, u0[md(s + 1 + kAhead, kU0Slots)],
+                     vs[md(s + 1 + kAhead, kStage)], ps[md(s + 1 + kAhead, kStage)], true);
 
             float un[4];
             // level T runs on a row of the segment (uniform)
@@ -174,17 +175,25 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
                     c = uw[t][md(s - t + 1, 3)];
                     so = uw[t][md(s - t + 2, 3)];
                 }
+                float pc[4];
+                if (t == 1) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) pc[e] = cp[e];
+                } else {
+                    const float4 q = phs[(i - t + 1) & (kPhiRows - 1)][lane];
+                    pc[0] = q.x; pc[1] = q.y; pc[2] = q.z; pc[3] = q.w;
+                }
                 const float west = from_west_lane(c[3]);
                 const float east = from_east_lane(c[0]);
                 // (west and east enter as a sum; the lane-shifted value goes
                 // first so the shift folds into the add)
-                cell_update(c[0], c[1], west, n[0], so[0], vr[rs][0], pr[rs][0], k, un[0],
+                cell_update(c[0], c[1], west, n[0], so[0], vr[rs][0], pc[0], k, un[0],
                             vr[rs][0]);
-                cell_update(c[1], c[0], c[2], n[1], so[1], vr[rs][1], pr[rs][1], k, un[1],
+                cell_update(c[1], c[0], c[2], n[1], so[1], vr[rs][1], pc[1], k, un[1],
                             vr[rs][1]);
-                cell_update(c[2], c[1], c[3], n[2], so[2], vr[rs][2], pr[rs][2], k, un[2],
+                cell_update(c[2], c[1], c[3], n[2], so[2], vr[rs][2], pc[2], k, un[2],
                             vr[rs][2]);
-                cell_update(c[3], c[2], east, n[3], so[3], vr[rs][3], pr[rs][3], k, un[3],
+                cell_update(c[3], c[2], east, n[3], so[3], vr[rs][3], pc[3], k, un[3],
                             vr[rs][3]);
                 if (t < T) {
                     // row rho of u^t: level t+1's newest row
@@ -225,6 +234,7 @@ template <int T>
 __global__ __launch_bounds__(kStreamWaves * 64, 2)
 void k_stream(StepArgs<float> a, StreamGeom g) {
     static_assert(stream_fits<T>(), "T too large for the row slots");
+    __shared__ float4 phs[kStreamWaves][kPhiRows][64];   // each wave's c1*phi ring
     constexpr int HX = stream_hx<T>();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -256,9 +266,9 @@ void k_stream(StepArgs<float> a, StreamGeom g) {
     // Interior strips load and store 16-byte words; a strip that reaches
     // past the left or right edge goes cell by cell.
     if (x_load0 >= 0 && x_load0 + 256 <= nx)
-        stream_pipeline<T, false>(a, ln, y0, y1);
+        stream_pipeline<T, false>(a, ln, y0, y1, phs[wave]);
     else
-        stream_pipeline<T, true>(a, ln, y0, y1);
+        stream_pipeline<T, true>(a, ln, y0, y1, phs[wave]);
 }
 
 // Items (strip, segment) for the streaming kernel: strips of `bx` output
@@ -333,6 +343,8 @@ hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s) {
         case 7: return stream_impl<7>(a, s);
         case 8: return stream_impl<8>(a, s);
         case 9: return stream_impl<9>(a, s);
+        case 10: return stream_impl<10>(a, s);
+        case 11: return stream_impl<11>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
