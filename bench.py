@@ -485,8 +485,12 @@ def bench_surrogate(args):
     own one-step predictions as inputs), then run on a 2048^2 circuit for
     50,000 steps with a plain-stepper check every 10 network steps and
     fallback when the front error exceeds one cell.  Reports its throughput
-    and speedup against the plain stepper on the same grid and schedule, the
-    tracked front error, and the roofline of the heaviest convolution."""
+    and speedup against the plain stepper (at its autotuned launch shape) on
+    the same grid and schedule twice: with every network step checked (the
+    run then continues from the plain result of every window, and its front
+    stays within one cell of the plain trajectory: the headline value), and
+    with every tenth step checked, at the front error a lock-step plain run
+    measures; and the roofline of the heaviest convolution."""
     import torch
     from paper_1901_06535_amd import inputs, rdc, surrogate as sg
 
@@ -526,8 +530,7 @@ def bench_surrogate(args):
     # plain stepper on the same schedule
     sim = rdc.Sim(wl.nx, wl.ny, wl.params, "fp32")
     sim.set_phi(wl.phi)
-    sim.set_block(8)
-    sim.set_tile_rows(56)
+    plain_shape = sim.autotune()          # the plain stepper at its best launch shape
 
     def plain_run():
         sim.write(zeros, zeros)
@@ -542,8 +545,8 @@ def bench_surrogate(args):
     t_plain = time.perf_counter() - t0
     plain_u = sim.current()[0].clone()
 
-    def coarse_run(track):
-        cs = sg.CoarseStepper(net, wl.nx, wl.ny, wl.params, wl.phi, K=K, check_every=10,
+    def coarse_run(track, check_every=10):
+        cs = sg.CoarseStepper(net, wl.nx, wl.ny, wl.params, wl.phi, K=K, check_every=check_every,
                               track=track)
         cs.write(zeros, zeros)
         torch.cuda.synchronize()
@@ -582,9 +585,18 @@ def bench_surrogate(args):
     cs_tr, _ = coarse_run(True)
     tracked = dict(cs_tr.stats)
     cs_tr.close()
+    # Every network step checked: the run continues from the plain result of
+    # every window, so its front error against the plain trajectory is the
+    # one setting that keeps it within one cell throughout (tracked below).
+    cs1, t_coarse1 = coarse_run(False, check_every=1)
+    stats1 = dict(cs1.stats)
+    cs1.close()
+    cs1_tr, _ = coarse_run(True, check_every=1)
+    tracked1 = dict(cs1_tr.stats)
+    cs1_tr.close()
     sim.close()
     cells = wl.nx * wl.ny
-    value = cells * wl.steps / t_coarse / 1e9
+    value = cells * wl.steps / t_coarse1 / 1e9
     achieved = fl / per[heavy] / 1e12
     nbytes = sg.conv_bytes(heavy, cs.ws)
     achieved_bw = nbytes / per[heavy] / 1e9
@@ -604,26 +616,37 @@ def bench_surrogate(args):
                             % (fl, nbytes, px_heavy))
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GCell-updates/s", "n_gpus": 1,
-        "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * t_coarse, 3),
+        "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * t_coarse1, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16 network (fp32 accumulate) + f32 plain checks", "data": "synthetic",
         "config": {"workload": "surrogate_circuit_2048x2048_50000steps", "K": K,
                    "check_every": 10, "train_pairs": iters * batch, "train_patch": patch,
                    "stimuli": len(wl.stimuli), "last_stimulus_step": max(s.step for s in wl.stimuli),
                    "parallelism": "single GPU"},
-        "speedup_vs_plain": round(t_plain / t_coarse, 4),
+        # value / ms_per_step: the setting whose front stays within one cell
+        # of the plain trajectory (every network step checked)
+        "speedup_vs_plain_at_le_1_cell": round(t_plain / t_coarse1, 4),
+        "at_le_1_cell": {"check_every": 1, "seconds": round(t_coarse1, 4), "coarse_stats": stats1,
+                         "tracked_windows": tracked1["tracked_windows"],
+                         "windows_more_than_1_cell_off": tracked1["windows_off"],
+                         "max_cells_more_than_1_cell_off": tracked1["max_cells_off"]},
+        "at_measured_error": {"check_every": 10, "seconds": round(t_coarse, 4),
+                              "speedup_vs_plain": round(t_plain / t_coarse, 4),
+                              "coarse_stats": stats,
+                              "tracked_windows": tracked["tracked_windows"],
+                              "windows_more_than_1_cell_off": tracked["windows_off"],
+                              "max_cells_more_than_1_cell_off": tracked["max_cells_off"],
+                              "final_cells_more_than_1_cell_off": final_off},
         "plain": {"seconds": round(t_plain, 4), "value": round(cells * wl.steps / t_plain / 1e9, 2),
-                  "unit": "GCell-updates/s", "steps_per_launch": 8, "tile_rows": 56},
-        "coarse_stats": stats,
-        "front_error": {"windows": tracked["tracked_windows"],
-                        "windows_more_than_1_cell_off": tracked["windows_off"],
-                        "max_cells_more_than_1_cell_off": tracked["max_cells_off"],
-                        "final_cells_more_than_1_cell_off": final_off},
+                  "unit": "GCell-updates/s", "steps_per_launch": plain_shape["T"],
+                  "tile_rows": plain_shape["rows"]},
         "training": {"seconds": round(t_train, 2), "iters": iters, "batch": batch,
                      "pushforward": pushforward,
                      "pairs_per_s": round(iters * batch / t_train, 1),
                      "loss_first_100": float(np.mean(losses[:100])),
-                     "loss_last_100": float(np.mean(losses[-100:])),
+                     "loss_last_100": float(np.nanmean(losses[-100:])),
+                     "dropped_batches_nonfinite_plain": tr.dropped_batches,
+                     "skipped_iters_nonfinite_loss": tr.skipped_iters,
                      "held_out_loss_net": l_net / 8, "held_out_loss_persistence": l_per / 8},
         "forward_ms_2048": round(whole_ms, 3),
         "forward_conv_ms_2048": round(1e3 * fwd_s, 3),

@@ -577,6 +577,17 @@ class BatchSim:
         _bcheck(s, self.b)
         return u, v
 
+    def nonfinite(self):
+        """Indices of the grids whose sticky non-finite flag is set (syncs)."""
+        out = []
+        for i in range(len(self.shapes)):
+            s = load().rdc_batch_read(self.b, i, None, None, 0, RDC_HOST)
+            if s == RDC_E_NONFINITE:
+                out.append(i)
+            else:
+                _bcheck(s, self.b)
+        return out
+
     def current(self):
         """Flat torch views (pool_elems,) of the pool planes holding u and v."""
         u = ctypes.c_void_p()

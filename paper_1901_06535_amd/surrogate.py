@@ -443,6 +443,8 @@ class Trainer:
             torch.empty_like(self.u_in) for _ in range(4))
         self.prev_ok = False
         self.round = 0
+        self.dropped_batches = 0      # batches with a non-finite plain grid (never trained on)
+        self.skipped_iters = 0        # iterations whose loss was not finite (no update made)
         self._new_sims()
 
     def _new_sims(self):
@@ -473,17 +475,25 @@ class Trainer:
 
     def pair(self):
         """Copies the current states to (u_in, v_in), advances K plain steps;
-        returns device addresses (u, v, phi, u_target, v_target)."""
-        if self.now + self.K > self.burn_in + 40 * self.K:
-            self.sims.close()
-            self._new_sims()
-            self.prev_ok = False
-        u, v = self.sims.current()
-        s = self.net.stream.cuda_stream
-        nb = 4 * self.batch * self.plane
-        rdc.rdc_copy(_ptr(self.u_in), _ptr(u), nb, s)
-        rdc.rdc_copy(_ptr(self.v_in), _ptr(v), nb, s)
-        self._advance(self.K)
+        returns device addresses (u, v, phi, u_target, v_target).  Pairs come
+        from finite plain trajectories only: a batch in which any grid has
+        set its non-finite flag (a stiff circuit whose refractory tail left
+        the Euler scheme's stable range) is dropped and a fresh one drawn."""
+        while True:
+            if self.now + self.K > self.burn_in + 40 * self.K:
+                self.sims.close()
+                self._new_sims()
+                self.prev_ok = False
+            u, v = self.sims.current()
+            s = self.net.stream.cuda_stream
+            nb = 4 * self.batch * self.plane
+            rdc.rdc_copy(_ptr(self.u_in), _ptr(u), nb, s)
+            rdc.rdc_copy(_ptr(self.v_in), _ptr(v), nb, s)
+            self._advance(self.K)
+            if not self.sims.nonfinite():
+                break
+            self.dropped_batches += 1
+            self.now = self.burn_in + 40 * self.K          # draw a fresh batch
         ut, vt = self.sims.current()
         return (_ptr(self.u_in), _ptr(self.v_in), _ptr(self.sims.planes[4]), _ptr(ut), _ptr(vt))
 
@@ -510,6 +520,9 @@ class Trainer:
         prep(self.net, self.ws, u, v, phi, self.pitch, self.plane)
         forward(self.net, self.ws)
         L = loss_and_grad(self.net, self.ws, u, v, ut, vt, self.pitch, self.plane)
+        if not np.isfinite(L):
+            self.skipped_iters += 1               # keep the weights finite
+            return L
         backward(self.net, self.ws)
         self.net.adam(lr=lr)
         return L
