@@ -140,8 +140,10 @@ def main():
     ap.add_argument("--T", type=int, default=0, help="steps per launch (0 = autotune)")
     ap.add_argument("--rows", type=int, default=0, help="tile rows (0 = autotune)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-per-grid", action="store_true",
+                    help="batch workloads: skip the per-grid-context baseline")
     ap.add_argument("--workload", default="uniform",
-                    choices=("uniform", "circuit", "batch", "surrogate", "variants"),
+                    choices=("uniform", "circuit", "batch", "batch_small", "surrogate", "variants"),
                     help="uniform: 16384^2, phi ~ U[0.04, 0.08), 64 disks, 2,000 steps "
                          "(default); circuit: 4096^2 circuit map, 256 disks, 10,000 steps; "
                          "batch: 512-grid sweep, 5,000 steps, batched vs per-grid; surrogate: "
@@ -156,6 +158,8 @@ def main():
                  "(--gpus %d requested)" % args.gpus)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "batch_small":
+        return bench_batch(args, small=True)
     if args.workload == "variants":
         return bench_variants(args)
     if args.workload == "surrogate":
@@ -296,18 +300,24 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def bench_batch(args):
+def bench_batch(args, small=False):
     """512 independent grids (sides log-uniform in [64, 1024], own eps and
     phi_excitable, channel lattices, 1-4 disks at t=0), 5,000 steps: one
-    batched launch per T steps replayed from a HIP graph, against stepping
-    each grid through its own single-grid context."""
+    batched launch per T steps for the tiled grids and one whole-grid launch
+    for the small ones, replayed from a HIP graph; against the same batch
+    with every grid tiled, and against stepping each grid through its own
+    single-grid context.  With `small`, 1,024 grids with sides in [64, 128]
+    (every one on the whole-grid path)."""
     import torch
     from paper_1901_06535_amd import inputs, rdc
 
     if not os.path.exists(rdc.LIB_PATH):
         from paper_1901_06535_amd import build
         build.build()
-    sims, steps = inputs.batch_sweep(count=512, seed=1004)
+    if small:
+        sims, steps = inputs.batch_sweep(count=1024, seed=1006, smin=64, smax=128)
+    else:
+        sims, steps = inputs.batch_sweep(count=512, seed=1004)
     cells = sum(s.nx * s.ny for s in sims)
     b = rdc.BatchSim([(s.nx, s.ny, s.params) for s in sims])
     for i, s in enumerate(sims):
@@ -340,6 +350,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / 1e3
     value = cells * steps * args.steps / t / 1e9
+    resident = b.resident_count()
     diverged = []
     for i in range(len(sims)):
         try:
@@ -350,13 +361,34 @@ def bench_batch(args):
             diverged.append(i)
     bu, bv = (t.clone() for t in b.current())       # the batch's final states (pooled)
     g.close()
+    # the same batch with every grid tiled (one run, after a warm-up run)
+    b.set_resident(0)
+    g = b.capture(steps)
+    reset()
+    g.launch()
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record(b.stream)
+    reset()
+    g.launch()
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    t_tiled = e0.elapsed_time(e1) / 1e3
+    tu, tv = b.current()
+
+    def grid(plane, i):
+        nx, ny, pitch, off = b.shapes[i]
+        return plane[off:off + ny * pitch].view(ny, pitch)[:, :nx]
+    tiled_same = all(torch.equal(grid(tu, i), grid(bu, i)) and torch.equal(grid(tv, i), grid(bv, i))
+                     for i in range(len(sims)) if i not in diverged)
+    g.close()
     b.close()
     del zeros
 
     # per-grid baseline: each grid through its own context, same T and tile
     # rows; contexts, phi and disks are set up before the timed region
     ctxs = []
-    for s in sims:
+    for s in ([] if args.no_per_grid else sims):
         sim = rdc.Sim(s.nx, s.ny, s.params, "fp32")
         sim.set_phi(s.phi)
         sim.set_block(T)
@@ -371,7 +403,7 @@ def bench_batch(args):
         sim.step(steps)
     e1.record()
     torch.cuda.synchronize()
-    t_single = e0.elapsed_time(e1) / 1e3
+    t_single = e0.elapsed_time(e1) / 1e3 if ctxs else float("nan")
     wall_single = time.perf_counter() - t0
     # every finite grid must end bit-identical to the same grid stepped alone
     same = 0
@@ -385,18 +417,32 @@ def bench_batch(args):
     for sim in ctxs:
         sim.close()
     single = cells * steps / t_single / 1e9
+    per_grid = None if not ctxs else {
+        "value": round(single, 2), "unit": "GCell-updates/s", "seconds": round(t_single, 3),
+        "wall_s": round(wall_single, 3), "speedup": round(value / single, 2),
+        "finite_grids_bitwise_equal": "%d/%d" % (same, len(sims) - len(diverged))}
+    roof = None
+    if resident == len(sims):
+        # one whole-grid launch per run: ALU-bound (no HBM traffic between steps)
+        ach = 21.0 * cells * steps * args.steps / t / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 2), "peak": 78.6, "unit": "TFLOP/s",
+                "frac": round(ach / 78.6, 4), "traffic": None, "kernel": "k_batch_resident",
+                "launch_ms": round(1e3 * t / args.steps, 3),
+                "algorithmic": "21 FLOP/update x %d cells x %d steps per launch" % (cells, steps)}
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GCell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "batched_sweep_512_grids_%dsteps" % steps, "grids": len(sims),
-                   "cells": cells, "steps_per_run": steps, "steps_per_launch": T,
-                   "tile_rows": rows, "graph": True, "parallelism": "single GPU"},
-        "per_grid_baseline": {"value": round(single, 2), "unit": "GCell-updates/s",
-                              "seconds": round(t_single, 3), "wall_s": round(wall_single, 3)},
-        "speedup_vs_per_grid": round(value / single, 2),
-        "finite_grids_bitwise_equal_to_per_grid": "%d/%d" % (same, len(sims) - len(diverged)),
+        "config": {"workload": "batched_sweep_%s%d_grids_%dsteps"
+                               % ("small_" if small else "", len(sims), steps),
+                   "grids": len(sims), "cells": cells, "steps_per_run": steps,
+                   "steps_per_launch": T, "tile_rows": rows, "graph": True,
+                   "whole_grid_lds_grids": resident, "parallelism": "single GPU"},
+        "all_tiled": {"value": round(cells * steps / t_tiled / 1e9, 2), "seconds": round(t_tiled, 4),
+                      "finite_grids_bitwise_equal": tiled_same},
+        "roofline": roof,
+        "per_grid_baseline": per_grid,
         "diverged_grids": len(diverged),
         "diverged_eps_max": round(max(sims[i].params["eps"] for i in diverged), 5) if diverged else None,
         "tuning_us_per_step": tune,

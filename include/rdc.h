@@ -217,9 +217,9 @@ const char *rdc_status_string(rdc_status s);
  * Batched simulations: many independent grids, each with its own size,
  * parameters and phi map (parameter sweeps and circuit variants, the paper's
  * reproducibility aim of Sec. 1 and Sec. 5), advanced together: one launch
- * covers every tile of every grid.  FP32 only; the per-cell update is the
- * same as rdc_step's, so each grid evolves bit-identically to a single
- * context with the same T.
+ * covers every tile of every grid, and small grids run whole in LDS (see
+ * rdc_batch_set_resident).  FP32 only; the per-cell update is the same as
+ * rdc_step's, so each grid evolves bit-identically to a single context.
  * ------------------------------------------------------------------------ */
 typedef struct rdc_batch rdc_batch; /* opaque */
 typedef struct rdc_graph rdc_graph; /* opaque: a recorded sequence of launches */
@@ -253,6 +253,27 @@ rdc_status rdc_batch_destroy(rdc_batch *b);
  * 56) of the batched kernel.  Does not change results. */
 rdc_status rdc_batch_set_block(rdc_batch *b, int32_t T, int32_t rows);
 
+/* Whole-grid path for small grids (same scheme, Sec. 2 Eq. (1)): a grid of
+ * at most max_cells cells whose shape fits one workgroup (nx <= 1024 and
+ * ceil(ny / floor(1024 / nx)) <= 16 rows per thread; every 128 x 128 grid
+ * does) is read once per rdc_batch_step call, advanced through all n steps
+ * in LDS and registers by one workgroup (one barrier per step, no HBM
+ * traffic in between) and written back once.  These launches run on a
+ * second stream of the batch, forked from its stream before the tiled
+ * grids' launches and joined into it after (so captures record them too).
+ * max_cells = 0 turns the path off; the default is
+ * RDC_BATCH_RESIDENT_DEFAULT (128 x 128).  Does not change results.  Waits
+ * for the batch's stream; a graph captured before the call refers to the
+ * old plan and its rdc_graph_launch returns RDC_E_STATE.  Errors:
+ * RDC_E_INVAL for max_cells < 0; RDC_E_NOMEM / RDC_E_DEVICE for the item
+ * table. */
+#define RDC_BATCH_RESIDENT_DEFAULT 16384
+rdc_status rdc_batch_set_resident(rdc_batch *b, int32_t max_cells);
+
+/* Number of grids the whole-grid path takes under the current setting (-1
+ * for NULL). */
+int32_t rdc_batch_resident_count(const rdc_batch *b);
+
 /* Copy phi of simulation `sim` (ny rows of `pitch` elements, host or
  * device).  Errors: RDC_E_INVAL for a bad index, NULL or pitch < nx. */
 rdc_status rdc_batch_set_phi(rdc_batch *b, int32_t sim, const void *phi, int64_t pitch,
@@ -282,8 +303,9 @@ rdc_status rdc_batch_read(rdc_batch *b, int32_t sim, void *u, void *v, int64_t p
  * needed) and is made once from each ping-pong copy of the planes; a replay
  * runs the one that starts from the copy holding the current state, so
  * eager rdc_batch_step calls may come between replays; n must be >= 2.
- * The graph refers to the batch, which must outlive it.  Errors:
- * RDC_E_INVAL for n < 2 or NULL; RDC_E_DEVICE if capture fails. */
+ * The graph refers to the batch, which must outlive it, and to its launch
+ * plan: after rdc_batch_set_resident, rdc_graph_launch returns RDC_E_STATE.
+ * Errors: RDC_E_INVAL for n < 2 or NULL; RDC_E_DEVICE if capture fails. */
 rdc_status rdc_batch_capture(rdc_batch *b, int64_t n, rdc_graph **out);
 rdc_status rdc_graph_launch(rdc_graph *g);
 rdc_status rdc_graph_destroy(rdc_graph *g);

@@ -2,13 +2,17 @@
 // together: the C ABI rdc_batch_* / rdc_graph_* of include/rdc.h and its
 // kernels.
 //
-// Every grid lives in its own region of five pooled planes.  A launch covers
-// a flat list of work items (grid, tile column, tile row) built once per
-// (T, tile rows); each 512-thread workgroup takes one item, reads that grid's
-// descriptor (size, pitch, plane offset, scheme constants) and runs the same
-// tile routine as the single-grid kernel, so a grid in a batch evolves
-// bit-identically to the same grid stepped alone.  A whole run can be
-// recorded into a HIP graph and replayed as one submission.
+// Every grid lives in its own region of five pooled planes.  Small grids
+// (at most a set number of cells, and a shape the whole-grid LDS kernel of
+// resident.hip takes) run every step of a call on chip, one workgroup each,
+// on a second stream forked from and joined back into the caller's.  The
+// others are stepped T steps per launch: a launch covers a flat list of work
+// items (grid, tile column, tile row) built once per (T, tile rows); each
+// 512-thread workgroup takes one item, reads that grid's descriptor (size,
+// pitch, plane offset, scheme constants) and runs the same tile routine as
+// the single-grid kernel.  Both paths use the one cell update, so a grid in
+// a batch evolves bit-identically to the same grid stepped alone.  A whole
+// run can be recorded into a HIP graph and replayed as one submission.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -19,6 +23,7 @@
 #include <vector>
 
 #include "../../include/rdc.h"
+#include "batch.h"
 #include "kernels.h"
 #include "tile.h"
 
@@ -26,12 +31,6 @@ namespace rdc {
 namespace {
 
 using namespace dev;
-
-struct SimDev {
-    int nx, ny;
-    int64_t pitch, offset;
-    Consts<float> k;
-};
 
 struct Item {
     int sim, tx, ty, pad;
@@ -160,7 +159,16 @@ struct rdc_batch {
     int64_t step = 0;
     rdc::SimDev* d_sims = nullptr;
     int* d_flags = nullptr;
+    // tile work items of the grids not taken by the resident kernel
     std::map<std::pair<int, int>, std::pair<rdc::Item*, int>> items;  // (T, rows) -> list
+    // whole-grid LDS path: cell limit, which grids it takes, their items
+    int32_t res_max_cells = RDC_BATCH_RESIDENT_DEFAULT;
+    std::vector<char> resident;
+    rdc::ResItem* d_res = nullptr;
+    int nres = 0;
+    hipStream_t side = nullptr;            // the resident launches' stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int64_t plan = 0;                      // bumped when the tables above are replaced
     std::string err;
 };
 
@@ -172,6 +180,7 @@ struct rdc_graph {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     int64_t n = 0;
+    int64_t plan = 0;                      // the batch's plan the recording refers to
 };
 
 namespace {
@@ -228,14 +237,16 @@ rdc_status items_for(rdc_batch* b, int T, int rows, const rdc::Item** out, int* 
         const int BY = rows - 2 * T;
         std::vector<rdc::Item> list;
         for (int s = 0; s < b->count; ++s) {
+            if (b->resident[s]) continue;
             const int tx_n = (b->sims[s].nx + BX - 1) / BX;
             const int ty_n = (b->sims[s].ny + BY - 1) / BY;
             for (int ty = 0; ty < ty_n; ++ty)
                 for (int tx = 0; tx < tx_n; ++tx) list.push_back({s, tx, ty, 0});
         }
         rdc::Item* d = nullptr;
-        hipError_t e = hipMalloc(&d, sizeof(rdc::Item) * list.size());
-        if (e == hipSuccess)
+        hipError_t e = hipSuccess;
+        if (!list.empty()) e = hipMalloc(&d, sizeof(rdc::Item) * list.size());
+        if (e == hipSuccess && !list.empty())
             e = hipMemcpy(d, list.data(), sizeof(rdc::Item) * list.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             if (d) (void)hipFree(d);
@@ -280,16 +291,96 @@ std::vector<int> plan_launches(int64_t n, int T, bool even) {
     return ks;
 }
 
-rdc_status run_launches(rdc_batch* b, const std::vector<int>& ks, hipStream_t s) {
-    for (const int k : ks) {
-        const rdc::Item* items = nullptr;
-        int n = 0;
-        rdc_status st = items_for(b, k, b->rows, &items, &n);
-        if (st != RDC_OK) return st;
-        hipError_t e = rdc::batch_launch_any(batch_args(b, items, n), k, b->rows, s);
-        if (e != hipSuccess) return bhip(b, e, "batched step launch");
-        b->cur ^= 1;
+// Advances every grid n steps: the tiled grids by the launches `ks` (steps
+// per launch) on stream s, the resident grids meanwhile by whole-grid
+// launches on the side stream, forked from s before and joined into s after
+// (event record / wait, which a stream capture records as graph edges).  The
+// resident grids read the planes the state is in and write the ones the
+// tiled grids end in (the same planes when the launch count is even: each
+// grid is read whole before any of it is written).
+rdc_status run_launches(rdc_batch* b, const std::vector<int>& ks, int64_t n, hipStream_t s) {
+    const bool tiled = b->nres < b->count;
+    const int start = b->cur;
+    const int end = tiled ? start ^ static_cast<int>(ks.size() & 1) : start;
+    const bool res = b->nres > 0 && n > 0;
+    hipError_t e = hipSuccess;
+    if (res) {
+        e = hipEventRecord(b->ev_fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+        for (int64_t done = 0; e == hipSuccess && done < n;) {
+            const int k = static_cast<int>(std::min<int64_t>(n - done, rdc::kResMaxSteps));
+            const int from = done == 0 ? start : end;
+            rdc::ResArgs a;
+            a.u = b->pool[from];
+            a.v = b->pool[2 + from];
+            a.phi = b->pool[4];
+            a.u_out = b->pool[end];
+            a.v_out = b->pool[2 + end];
+            a.sims = b->d_sims;
+            a.items = b->d_res;
+            a.flags = b->d_flags;
+            a.count = b->nres;
+            a.steps = k;
+            e = rdc::launch_resident(a, b->side);
+            done += k;
+        }
+        if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
+        if (e != hipSuccess) return bhip(b, e, "whole-grid launch");
     }
+    if (tiled) {
+        for (const int k : ks) {
+            const rdc::Item* items = nullptr;
+            int cnt = 0;
+            rdc_status st = items_for(b, k, b->rows, &items, &cnt);
+            if (st != RDC_OK) return st;
+            e = rdc::batch_launch_any(batch_args(b, items, cnt), k, b->rows, s);
+            if (e != hipSuccess) return bhip(b, e, "batched step launch");
+            b->cur ^= 1;
+        }
+    }
+    if (res) {
+        e = hipStreamWaitEvent(s, b->ev_join, 0);
+        if (e != hipSuccess) return bhip(b, e, "whole-grid join");
+    }
+    return RDC_OK;
+}
+
+// Which grids the whole-grid kernel takes (nx * ny <= max_cells and a shape
+// it holds), and its work-item table; the tile item tables are rebuilt.
+rdc_status set_resident(rdc_batch* b, int32_t max_cells) {
+    std::vector<rdc::ResItem> list;
+    std::vector<char> flag(b->count, 0);
+    for (int i = 0; i < b->count; ++i) {
+        const rdc_sim_desc& d = b->sims[i];
+        int m = 0, groups = 0;
+        if ((int64_t)d.nx * d.ny <= max_cells && rdc::resident_layout(d.nx, d.ny, &m, &groups)) {
+            list.push_back({i, m, groups, 0});
+            flag[i] = 1;
+        }
+    }
+    rdc::ResItem* d = nullptr;
+    hipError_t e = hipSuccess;
+    if (!list.empty()) e = hipMalloc(&d, sizeof(rdc::ResItem) * list.size());
+    if (e == hipSuccess && !list.empty())
+        e = hipMemcpy(d, list.data(), sizeof(rdc::ResItem) * list.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return bhip(b, e, "whole-grid item table");
+    }
+    // launches already queued may still read the old tables
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        return bhip(b, e, "device error before re-planning");
+    }
+    if (b->d_res) (void)hipFree(b->d_res);
+    for (auto& kv : b->items) (void)hipFree(kv.second.first);
+    b->items.clear();
+    b->d_res = d;
+    b->nres = static_cast<int>(list.size());
+    ++b->plan;
+    b->resident.swap(flag);
+    b->res_max_cells = max_cells;
     return RDC_OK;
 }
 
@@ -311,6 +402,24 @@ rdc_status copy_sim_plane(rdc_batch* b, int sim, float* pool, const void* src, i
     if (e == hipSuccess && where == RDC_HOST) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bhip(b, e, "plane copy");
     return RDC_OK;
+}
+
+// Device objects of a batch (also of one whose creation failed part way).
+void release(rdc_batch* b) {
+    if (b->side) (void)hipStreamSynchronize(b->side);
+    for (auto& kv : b->items) (void)hipFree(kv.second.first);
+    b->items.clear();
+    if (b->d_res) (void)hipFree(b->d_res);
+    if (b->d_sims) (void)hipFree(b->d_sims);
+    if (b->d_flags) (void)hipFree(b->d_flags);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    b->d_res = nullptr;
+    b->d_sims = nullptr;
+    b->d_flags = nullptr;
+    b->ev_fork = b->ev_join = nullptr;
+    b->side = nullptr;
 }
 
 }  // namespace
@@ -367,12 +476,18 @@ rdc_status rdc_batch_create(int32_t count, const rdc_sim_desc* sims, const rdc_b
                            b->d_flags, count);
         e = hipGetLastError();
     }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        const std::string m = std::string("device setup: ") + hipGetErrorString(e);
-        if (b->d_sims) (void)hipFree(b->d_sims);
-        if (b->d_flags) (void)hipFree(b->d_flags);
+    rdc_status st = RDC_OK;
+    if (e == hipSuccess) st = set_resident(b, RDC_BATCH_RESIDENT_DEFAULT);
+    if (e != hipSuccess || st != RDC_OK) {
+        const std::string m = e != hipSuccess ? std::string("device setup: ") + hipGetErrorString(e)
+                                              : b->err;
+        release(b);
         delete b;
+        if (st != RDC_OK) return bfail(nullptr, st, m);
         return bfail(nullptr, e == hipErrorOutOfMemory ? RDC_E_NOMEM : RDC_E_DEVICE, m);
     }
     *out = b;
@@ -383,12 +498,19 @@ rdc_status rdc_batch_destroy(rdc_batch* b) {
     if (!b) return RDC_OK;
     Dev g(b->device);
     (void)hipStreamSynchronize(b->stream);
-    for (auto& kv : b->items) (void)hipFree(kv.second.first);
-    if (b->d_sims) (void)hipFree(b->d_sims);
-    if (b->d_flags) (void)hipFree(b->d_flags);
+    release(b);
     delete b;
     return RDC_OK;
 }
+
+rdc_status rdc_batch_set_resident(rdc_batch* b, int32_t max_cells) {
+    if (!b) return RDC_E_INVAL;
+    if (max_cells < 0) return bfail(b, RDC_E_INVAL, "max_cells < 0");
+    Dev g(b->device);
+    return set_resident(b, max_cells);
+}
+
+int32_t rdc_batch_resident_count(const rdc_batch* b) { return b ? b->nres : -1; }
 
 rdc_status rdc_batch_set_block(rdc_batch* b, int32_t T, int32_t rows) {
     if (!b) return RDC_E_INVAL;
@@ -461,7 +583,7 @@ rdc_status rdc_batch_step(rdc_batch* b, int64_t n) {
     if (!b) return RDC_E_INVAL;
     if (n < 0) return bfail(b, RDC_E_INVAL, "n < 0");
     Dev g(b->device);
-    rdc_status s = run_launches(b, plan_launches(n, b->T, false), b->stream);
+    rdc_status s = run_launches(b, plan_launches(n, b->T, false), n, b->stream);
     if (s == RDC_OK) b->step += n;
     return s;
 }
@@ -528,7 +650,7 @@ rdc_status rdc_batch_capture(rdc_batch* b, int64_t n, rdc_graph** out) {
     for (int p = 0; p < 2 && e == hipSuccess && s == RDC_OK; ++p) {
         b->cur = p;
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) s = run_launches(b, ks, cs);
+        if (e == hipSuccess) s = run_launches(b, ks, n, cs);
         const hipError_t e2 = hipStreamEndCapture(cs, &gr->graph[p]);
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess && s == RDC_OK)
@@ -546,12 +668,16 @@ rdc_status rdc_batch_capture(rdc_batch* b, int64_t n, rdc_graph** out) {
     }
     gr->b = b;
     gr->n = n;
+    gr->plan = b->plan;
     *out = gr;
     return RDC_OK;
 }
 
 rdc_status rdc_graph_launch(rdc_graph* g) {
     if (!g || !g->b) return RDC_E_INVAL;
+    if (g->plan != g->b->plan)
+        return bfail(g->b, RDC_E_STATE, "the batch was re-planned (rdc_batch_set_resident) "
+                                        "after this graph was captured");
     Dev d(g->b->device);
     hipError_t e = hipGraphLaunch(g->exec[g->b->cur], g->b->stream);
     if (e != hipSuccess) return bhip(g->b, e, "graph launch");

@@ -26,6 +26,8 @@ NEVER = 0x7FFFFFFF
 # rdc_set_tile_rows value for the row-pipeline kernel (register-resident
 # strips instead of LDS tiles)
 RDC_TILE_STREAM = 1
+# default cell limit of the batches' whole-grid LDS path (rdc_batch_set_resident)
+RDC_BATCH_RESIDENT_DEFAULT = 16384
 
 # Every symbol include/rdc.h declares.
 EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_write",
@@ -35,7 +37,7 @@ EXPORTS = ("rdc_create", "rdc_destroy", "rdc_set_params", "rdc_set_phi", "rdc_wr
            "rdc_batch_create", "rdc_batch_destroy", "rdc_batch_set_block", "rdc_batch_set_phi",
            "rdc_batch_write", "rdc_batch_stimulate", "rdc_batch_step", "rdc_batch_read",
            "rdc_batch_capture", "rdc_graph_launch", "rdc_graph_destroy", "rdc_batch_last_error",
-           "rdc_batch_current",
+           "rdc_batch_current", "rdc_batch_set_resident", "rdc_batch_resident_count",
            "rdc_nn_conv3x3", "rdc_nn_conv3x3_up", "rdc_nn_conv3x3_planes",
            "rdc_nn_conv3x3_apply",
            "rdc_nn_dgrad_weights", "rdc_nn_wgrad_scratch_floats",
@@ -106,6 +108,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                    i64, vp, ctypes.POINTER(vp)]),
         "rdc_batch_destroy": (i32, [vp]),
         "rdc_batch_set_block": (i32, [vp, i32, i32]),
+        "rdc_batch_set_resident": (i32, [vp, i32]),
+        "rdc_batch_resident_count": (i32, [vp]),
         "rdc_batch_set_phi": (i32, [vp, i32, vp, i64, i32]),
         "rdc_batch_write": (i32, [vp, i32, vp, vp, i64, i32]),
         "rdc_batch_stimulate": (i32, [vp, i32p, i32p, i32p, i32p, i32]),
@@ -538,6 +542,13 @@ class BatchSim:
 
     def set_block(self, T: int, rows: int = 56) -> None:
         _bcheck(load().rdc_batch_set_block(self.b, T, rows), self.b)
+
+    def set_resident(self, max_cells: int) -> None:
+        """Grids of at most max_cells cells (that fit) run whole in LDS; 0 = off."""
+        _bcheck(load().rdc_batch_set_resident(self.b, int(max_cells)), self.b)
+
+    def resident_count(self) -> int:
+        return int(load().rdc_batch_resident_count(self.b))
 
     def autotune(self, **kw):
         """Time the launch shapes on these grids' shapes (cached) and use the

@@ -246,13 +246,37 @@ static void batch(void) {
     EXPECT(rdc_batch_set_block(bt, 13, 56) == RDC_E_INVAL);
     EXPECT(rdc_batch_set_block(bt, 12, 48) == RDC_OK);
     EXPECT(rdc_batch_set_block(bt, 6, 48) == RDC_OK);
+    /* all three grids fit the whole-grid path by default: one launch for 20 steps */
+    EXPECT(rdc_batch_resident_count(bt) == 3);
+    long l0 = shim_launches();
     EXPECT(rdc_batch_step(bt, 20) == RDC_OK);
+    EXPECT(shim_launches() - l0 == 1);
+    l0 = shim_launches();
+    EXPECT(rdc_batch_step(bt, 40000) == RDC_OK);    /* split into launches of <= 16384 steps */
+    EXPECT(shim_launches() - l0 == 3);
     EXPECT(rdc_batch_step(bt, -1) == RDC_E_INVAL);
     rdc_graph *g = NULL;
     EXPECT(rdc_batch_capture(bt, 1, &g) == RDC_E_INVAL);
     EXPECT(rdc_batch_capture(bt, 10, &g) == RDC_OK && g);
     EXPECT(rdc_graph_launch(g) == RDC_OK);
+    /* 100 x 70 only (4096 cells) on the whole-grid path, the others tiled */
+    EXPECT(rdc_batch_set_resident(bt, -1) == RDC_E_INVAL);
+    EXPECT(rdc_batch_set_resident(bt, 7000) == RDC_OK);
+    EXPECT(rdc_batch_resident_count(bt) == 2);       /* 100 x 70 and 64 x 64 */
+    EXPECT(rdc_graph_launch(g) == RDC_E_STATE);      /* recorded under the old plan */
     EXPECT(rdc_graph_destroy(g) == RDC_OK);
+    l0 = shim_launches();
+    EXPECT(rdc_batch_step(bt, 20) == RDC_OK);       /* 1 whole-grid + 4 tiled (T = 6) */
+    EXPECT(shim_launches() - l0 == 5);
+    EXPECT(rdc_batch_set_resident(bt, 0) == RDC_OK);
+    EXPECT(rdc_batch_resident_count(bt) == 0);
+    l0 = shim_launches();
+    EXPECT(rdc_batch_step(bt, 20) == RDC_OK);
+    EXPECT(shim_launches() - l0 == 4);
+    EXPECT(rdc_batch_capture(bt, 10, &g) == RDC_OK && g);
+    EXPECT(rdc_graph_launch(g) == RDC_OK);
+    EXPECT(rdc_graph_destroy(g) == RDC_OK);
+    EXPECT(rdc_batch_resident_count(NULL) == -1);
     void *cu = NULL, *cv = NULL;
     EXPECT(rdc_batch_current(bt, &cu, &cv) == RDC_OK && cu && cv);
     EXPECT(rdc_batch_last_error(bt) != NULL);

@@ -63,6 +63,18 @@ hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned flags) {
     return ok;
 }
 hipError_t hipStreamDestroy(hipStream_t s) { free(s); return ok; }
+typedef void *hipEvent_t;
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned flags) {
+    (void)flags;
+    *e = malloc(16);
+    return ok;
+}
+hipError_t hipEventDestroy(hipEvent_t e) { free(e); return ok; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) { (void)s; return e ? ok : invalid_value; }
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned flags) {
+    (void)s; (void)flags;
+    return e ? ok : invalid_value;
+}
 hipError_t hipStreamBeginCapture(hipStream_t s, int mode) {
     (void)s; (void)mode;
     capturing = 1;

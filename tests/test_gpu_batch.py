@@ -1,6 +1,7 @@
 """Batched simulations on the GPU: every grid of a batch evolves bit-identically
-to the same grid stepped alone (same per-cell expression), graph replays equal
-eager stepping, and batched grids match the FP64 oracle."""
+to the same grid stepped alone (same per-cell expression), whether it runs
+tiled or whole in LDS (the small grids' path), graph replays equal eager
+stepping, and batched grids match the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -170,3 +171,98 @@ def test_sweep_workload_stability_matches_the_oracle():
         run.stimulate([(d.cx, d.cy, d.r) for d in s.stimuli])
         run.advance(2000)
         assert not (np.isfinite(run.u).all() and np.isfinite(run.v).all())
+
+
+# ---------------------------------------------------------------- whole-grid LDS path
+
+# Shapes of the whole-grid kernel's layouts: one column per thread with 1..16
+# rows, full and ragged last row groups, single rows and columns, the widest
+# (1024 columns) and the largest (128 x 128) grids; the last one is tiled.
+RES_SIZES = [(1, 7), (7, 1), (2, 3000), (1000, 10), (1024, 16), (128, 128), (37, 199),
+             (333, 41), (100, 70), (16, 16), (300, 200)]
+
+
+def _res_case(seed):
+    rng = np.random.default_rng(seed)
+    specs, states, disks = [], [], []
+    for i, (nx, ny) in enumerate(RES_SIZES):
+        p = dict(inputs.PARAMS_WORKLOAD)
+        p["eps"] = float(rng.uniform(0.022, 0.03))
+        u, v, phi = inputs.random_state(nx, ny, seed=300 + i, umax=0.02, vmax=0.02)
+        specs.append((nx, ny, p))
+        states.append((u, v, phi))
+        disks.append((i, nx // 3, ny // 2, 4))
+    return specs, states, disks
+
+
+@pytest.mark.parametrize("n,T", [(37, 8), (45, 8), (12, 12)])
+def test_resident_layouts_equal_single_grids_bitwise(n, T):
+    """n steps with T = 8 take 5 (odd: the whole-grid launches write the
+    other ping-pong copy) or 6 tile launches; 12 at T = 12 one."""
+    specs, states, disks = _res_case(seed=21)
+    b = _batch(specs, states, disks, T)
+    assert b.resident_count() == len(RES_SIZES) - 1
+    print("[case] resident layouts n=%d T=%d" % (n, T), flush=True)
+    b.step(n)
+    for i in range(len(specs)):
+        got = b.read(i)
+        ref = _single(specs[i], states[i], disks[i], 8, n)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (i, RES_SIZES[i])
+    b.close()
+
+
+def test_resident_path_equals_tiled_path_bitwise():
+    specs, states, disks = _case(seed=13)
+    res = _batch(specs, states, disks, 8)
+    tiled = _batch(specs, states, disks, 8)
+    tiled.set_resident(0)
+    small = sum(nx * ny <= rdc.RDC_BATCH_RESIDENT_DEFAULT for nx, ny, _ in specs)
+    assert res.resident_count() == small and tiled.resident_count() == 0
+    for n in (19, 8, 40):
+        res.step(n)
+        tiled.step(n)
+        for i in range(len(specs)):
+            a, c = res.read(i), tiled.read(i)
+            assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1]), (n, i)
+    res.close()
+    tiled.close()
+
+
+def test_resident_long_call_is_split_and_bitwise():
+    """40,000 steps in one call: three whole-grid launches (16,384 steps at
+    most each) on an all-small batch."""
+    specs, states, disks = _res_case(seed=22)
+    pick = [9, 8]                                   # 16 x 16 and 100 x 70
+    specs = [specs[i] for i in pick]
+    states = [states[i] for i in pick]
+    disks = [(j,) + disks[i][1:] for j, i in enumerate(pick)]
+    b = _batch(specs, states, disks, 8)
+    assert b.resident_count() == 2
+    b.step(40000)
+    for j in range(2):
+        got = b.read(j)
+        ref = _single(specs[j], states[j], disks[j], 12, 40000)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), j
+    b.close()
+
+
+def test_resident_graph_and_replan():
+    """A graph recorded with whole-grid launches replays like eager steps;
+    after rdc_batch_set_resident the old recording is refused."""
+    specs, states, disks = _res_case(seed=23)
+    eager = _batch(specs, states, disks, 8)
+    graph_b = _batch(specs, states, disks, 8)
+    g = graph_b.capture(40)
+    for rep in range(2):
+        eager.step(40)
+        g.launch()
+        for i in range(len(specs)):
+            a, c = eager.read(i), graph_b.read(i)
+            assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1]), (rep, i)
+    graph_b.set_resident(4096)
+    with pytest.raises(rdc.RdcError) as e:
+        g.launch()
+    assert e.value.status == rdc.RDC_E_STATE
+    g.close()
+    eager.close()
+    graph_b.close()
