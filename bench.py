@@ -333,9 +333,14 @@ def bench_batch(args, small=False):
             rdc.rdc_copy(plane.data_ptr(), zeros.data_ptr(), nbytes, stream)
         b.stimulate(disks)
 
-    # autotune the batched launch on the sweep's shapes
-    rec = b.autotune(launches=24, use_cache=False)
-    T, rows, tune = rec["T"], rec["rows"], rec["table"]
+    # autotune the tiled grids' launch shape on the sweep's shapes (nothing
+    # to tune when every grid is on the whole-grid path)
+    if b.resident_count() < len(sims):
+        rec = b.autotune(launches=24, use_cache=False)
+        T, rows, tune = rec["T"], rec["rows"], rec["table"]
+    else:
+        T, rows, tune = 8, 56, None
+        b.set_block(T, rows)
     g = b.capture(steps)
     for _ in range(args.warmup):
         reset()
@@ -361,8 +366,11 @@ def bench_batch(args, small=False):
             diverged.append(i)
     bu, bv = (t.clone() for t in b.current())       # the batch's final states (pooled)
     g.close()
-    # the same batch with every grid tiled (one run, after a warm-up run)
+    # the same batch with every grid tiled (one run, after a warm-up run), at
+    # its own best launch shape
     b.set_resident(0)
+    if tune is None:
+        b.autotune(launches=24, use_cache=False)
     g = b.capture(steps)
     reset()
     g.launch()

@@ -128,18 +128,21 @@ def tune_sim(sim, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = DEFAULT_R
 
 def tune_batch(batch, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = (48, 56, 64),
                launches: int = 24, use_cache: bool = True) -> Dict:
-    """Pick (T, rows) for an `rdc.BatchSim` (keyed by its list of grid
-    sizes), set them and return the record."""
+    """Pick (T, rows) for an `rdc.BatchSim` (keyed by its list of grid sizes
+    and its whole-grid path setting, which decides the grids that are
+    tiled), set them and return the record."""
     import hashlib
     from . import rdc
     sizes = ",".join("%dx%d" % (nx, ny) for nx, ny, _, _ in batch.shapes)
-    key = key_for("batch", "%d:%s" % (len(batch.shapes),
-                                      hashlib.sha256(sizes.encode()).hexdigest()[:16]))
+    res = batch.resident_max_cells
+    key = key_for("batch", "%d:%s:res%d" % (len(batch.shapes),
+                                            hashlib.sha256(sizes.encode()).hexdigest()[:16], res))
     hit = _load().get(key) if use_cache else None
     if hit:
         rec = dict(hit, cached=True)
     else:
         scratch = rdc.BatchSim(batch.specs, device=batch.device, stream=batch.stream)
+        scratch.set_resident(res)             # the same grids tiled as in `batch`
         Ts = [T for T in Ts if T <= MAX_T["fp32"]]
         (T, r), table = _search(scratch.step, scratch.set_block, scratch.stream, Ts, rows,
                                 launches)

@@ -358,6 +358,16 @@ rdc_status set_resident(rdc_batch* b, int32_t max_cells) {
             flag[i] = 1;
         }
     }
+    // Longest first: workgroups start in index order as CUs free up (one
+    // grid per CU at a time), and a grid's time is about its rows per thread
+    // times its waves, so this order keeps the CUs' finishing times even.
+    auto cost = [&](const rdc::ResItem& r) {
+        const int64_t waves = ((int64_t)r.groups * b->sims[r.sim].nx + 63) / 64;
+        return waves * r.m;
+    };
+    std::stable_sort(list.begin(), list.end(), [&](const rdc::ResItem& a, const rdc::ResItem& c) {
+        return cost(a) > cost(c);
+    });
     rdc::ResItem* d = nullptr;
     hipError_t e = hipSuccess;
     if (!list.empty()) e = hipMalloc(&d, sizeof(rdc::ResItem) * list.size());

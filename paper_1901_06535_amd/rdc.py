@@ -532,6 +532,7 @@ class BatchSim:
                                          self.stream.cuda_stream or None, ctypes.byref(out)), None)
         self.b = out.value
         self.step_index = 0
+        self.resident_max_cells = RDC_BATCH_RESIDENT_DEFAULT
 
     def _host(self, i, a):
         nx, ny, _, _ = self.shapes[i]
@@ -546,6 +547,7 @@ class BatchSim:
     def set_resident(self, max_cells: int) -> None:
         """Grids of at most max_cells cells (that fit) run whole in LDS; 0 = off."""
         _bcheck(load().rdc_batch_set_resident(self.b, int(max_cells)), self.b)
+        self.resident_max_cells = int(max_cells)
 
     def resident_count(self) -> int:
         return int(load().rdc_batch_resident_count(self.b))
