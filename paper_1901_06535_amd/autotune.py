@@ -24,8 +24,8 @@ from .profile_kernels import source_hash
 DEFAULT_T = (4, 6, 8, 9, 10, 11, 12)
 # LDS tile heights, and 1 = the row-pipeline kernel (rdc.RDC_TILE_STREAM)
 DEFAULT_ROWS = (48, 56, 64, 80, 1)
-# Most steps per launch the row-pipeline kernel takes (FP32 only).
-MAX_T_STREAM = 11
+# Most steps per launch the row-pipeline kernels take, per precision.
+MAX_T_STREAM = {"fp32": 11, "fp64": 8}
 # Most steps per launch the library's tile kernels take, per precision
 # (rdc_set_block; the batched kernels are FP32).
 MAX_T = {"fp32": 12, "fp64": 8}
@@ -83,11 +83,12 @@ def _time(step, set_shape, stream, T: int, rows: int, launches: int) -> float:
 
 
 def _search(step, set_shape, stream, Ts: Iterable[int], rows: Iterable[int],
-            launches: int) -> Tuple[Tuple[int, int], Dict[str, float]]:
+            launches: int, max_stream: int = MAX_T_STREAM["fp32"]
+            ) -> Tuple[Tuple[int, int], Dict[str, float]]:
     table = {}
     for T in Ts:
         for r in rows:
-            if r == 1 and T > MAX_T_STREAM:
+            if r == 1 and T > max_stream:
                 continue                      # such launches would run as 56-row tiles
             table["T%d_r%d" % (T, r)] = _time(step, set_shape, stream, T, r, launches)
     best = min(table, key=table.get)
@@ -109,13 +110,12 @@ def tune_sim(sim, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = DEFAULT_R
         scratch = rdc.Sim(sim.nx, sim.ny, sim.params, sim.dtype, device=sim.device,
                           stream=sim.stream)
         Ts = [T for T in Ts if T <= MAX_T[sim.dtype]]
-        if sim.dtype != "fp32":
-            rows = [r for r in rows if r != 1]
 
         def set_shape(T, r):
             scratch.set_block(T)
             scratch.set_tile_rows(r)
-        (T, r), table = _search(scratch.step, set_shape, scratch.stream, Ts, rows, launches)
+        (T, r), table = _search(scratch.step, set_shape, scratch.stream, Ts, rows, launches,
+                                MAX_T_STREAM[sim.dtype])
         scratch.close()
         rec = {"T": T, "rows": r, "us_per_step": round(1e6 * table["T%d_r%d" % (T, r)], 3),
                "table": {k: round(1e6 * v, 3) for k, v in table.items()}}

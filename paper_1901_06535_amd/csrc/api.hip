@@ -318,9 +318,10 @@ rdc_status rdc_step(rdc_ctx* c, int64_t n) {
         if (k == 1)
             e = f64 ? rdc::launch_step1(step_args<double>(c), c->stream)
                     : rdc::launch_step1(step_args<float>(c), c->stream);
-        else if (rows == RDC_TILE_STREAM && !f64 && rdc::stream_supported(k) && !c->arrival &&
-                 !c->tl)
-            e = rdc::launch_stream(step_args<float>(c), k, c->stream);
+        else if (rows == RDC_TILE_STREAM && !c->arrival && !c->tl &&
+                 (f64 ? rdc::stream64_supported(k) : rdc::stream_supported(k)))
+            e = f64 ? rdc::launch_stream(step_args<double>(c), k, c->stream)
+                    : rdc::launch_stream(step_args<float>(c), k, c->stream);
         else
             e = f64 ? rdc::launch_stepT(step_args<double>(c), k, tile_rows, c->stream)
                     : rdc::launch_stepT(step_args<float>(c), k, tile_rows, c->stream);

@@ -68,6 +68,18 @@ struct StreamGeom {
 };
 bool stream_supported(int T);
 hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s);
+// The same for FP64 (128-column strips, 2 cells per lane), T in 2..kMaxStream64.
+constexpr int kMaxStream64 = 8;
+bool stream64_supported(int T);
+hipError_t launch_stream(const StepArgs<double>& a, int T, hipStream_t s);
+// Strips of `bx` output columns and row segments for the row-pipeline
+// kernels (4 waves per workgroup, ticks counted in loop bodies of 12):
+// segments of near-equal height, as many as keep lowest the rows walked
+// per round of `slots` resident waves.
+StreamGeom stream_geom(int nx, int ny, int T, int bx, int slots);
+// Resident waves of a row-pipeline launch on the current device (two 4-wave
+// workgroups per CU).
+int stream_slots();
 
 // Catalytic stimulation: u := 1 on up to kMaxDisks disks per launch.
 constexpr int kMaxDisks = 64;

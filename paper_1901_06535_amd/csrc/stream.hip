@@ -271,6 +271,20 @@ void k_stream(StepArgs<float> a, StreamGeom g) {
         stream_pipeline<T, true>(a, ln, y0, y1, phs[wave]);
 }
 
+template <int T>
+hipError_t stream_impl(const StepArgs<float>& a, hipStream_t s) {
+    constexpr int HX = stream_hx<T>();
+    // Output columns: the loaded 256 less the left halo HX and a right halo
+    // of at least T, kept a multiple of 4.
+    constexpr int bx = (256 - HX - T) & ~3;
+    const StreamGeom g = stream_geom(a.nx, a.ny, T, bx, stream_slots());
+    const dim3 grid(8 * g.per_xcd), block(kStreamWaves * 64);
+    hipLaunchKernelGGL((k_stream<T>), grid, block, 0, s, a, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 // Items (strip, segment) for the streaming kernel: strips of `bx` output
 // columns; segments of near-equal height, as many as keep lowest the rows
 // walked per round of resident waves (`slots` waves at a time).
@@ -300,7 +314,7 @@ StreamGeom stream_geom(int nx, int ny, int T, int bx, int slots) {
     return g;
 }
 
-int device_slots() {
+int stream_slots() {
     // Resident waves when every CU holds two 4-wave workgroups (the launch
     // bounds ask for two waves per SIMD).
     static int cached_dev = -1, cached = 0;
@@ -316,20 +330,6 @@ int device_slots() {
     }
     return cached;
 }
-
-template <int T>
-hipError_t stream_impl(const StepArgs<float>& a, hipStream_t s) {
-    constexpr int HX = stream_hx<T>();
-    // Output columns: the loaded 256 less the left halo HX and a right halo
-    // of at least T, kept a multiple of 4.
-    constexpr int bx = (256 - HX - T) & ~3;
-    const StreamGeom g = stream_geom(a.nx, a.ny, T, bx, device_slots());
-    const dim3 grid(8 * g.per_xcd), block(kStreamWaves * 64);
-    hipLaunchKernelGGL((k_stream<T>), grid, block, 0, s, a, g);
-    return hipGetLastError();
-}
-
-}  // namespace
 
 bool stream_supported(int T) { return T >= 2 && T <= kMaxStream; }
 

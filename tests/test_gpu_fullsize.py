@@ -87,6 +87,26 @@ def test_fp64_bitwise_at_samples(case):
     assert np.array_equal(a3[:, 1, 1], ref["arr3"][:, 1, 1])
 
 
+def test_fp64_row_pipelines_bitwise_at_samples(case):
+    """The FP64 row-pipeline kernel at full size (no arrival map attached, so
+    every launch takes it): u and v at the sample cells equal the oracle's."""
+    import torch
+    name, wl, ref = case
+    print("[case] fp64 row pipelines %s T=8" % name, flush=True)
+    s = rdc.Sim(wl.nx, wl.ny, wl.params, "fp64")
+    s.set_phi(wl.phi.astype(np.float64))
+    s.write(wl.u0, wl.v0)
+    s.set_block(8)
+    s.set_tile_rows(rdc.RDC_TILE_STREAM)
+    s.run_schedule(wl.stimuli, wl.steps)
+    u, v = s.current()
+    iy = torch.as_tensor(ref["idx"][:, 0], device=u.device, dtype=torch.long)
+    ix = torch.as_tensor(ref["idx"][:, 1], device=u.device, dtype=torch.long)
+    gu, gv = u[iy, ix].cpu().numpy(), v[iy, ix].cpu().numpy()
+    s.close()
+    assert np.array_equal(gu, ref["u"]) and np.array_equal(gv, ref["v"])
+
+
 @pytest.mark.parametrize("T,rows", [(8, 56), (8, 64), (10, 64), (11, 64), (12, 56)])
 def test_fp32_bench_launch_shape_at_samples(case, T, rows):
     name, wl, ref = case

@@ -104,9 +104,10 @@ def _ragged_case(nx=333, ny=275, seed=12):
     return u, v, phi, [(d.cx, d.cy, d.r) for d in disks]
 
 
-def _run_fp32(u, v, phi, disks, T, rows, nsteps=(23, 14), params=inputs.PARAMS_WORKLOAD):
+def _run_fp32(u, v, phi, disks, T, rows, nsteps=(23, 14), params=inputs.PARAMS_WORKLOAD,
+              dtype="fp32"):
     ny, nx = u.shape
-    s = rdc.Sim(nx, ny, params, "fp32")
+    s = rdc.Sim(nx, ny, params, dtype)
     s.set_phi(phi)
     s.write(u, v)
     s.set_block(T)
@@ -166,7 +167,7 @@ def test_every_fp64_launch_shape_is_bitwise_equal_to_the_oracle():
     run.advance(23)
     run.stimulate(disks[:3])
     run.advance(14)
-    for rows in (48, 56, 64, 80):
+    for rows in (48, 56, 64, 80, rdc.RDC_TILE_STREAM):
         for T in range(2, 9):
             print_case("fp64 T=%d rows=%d" % (T, rows))
             s = rdc.Sim(nx, ny, inputs.PARAMS_WORKLOAD, "fp64")
@@ -215,6 +216,26 @@ def test_row_pipelines_across_strips_and_segments_bitwise(ny, nx):
         print_case("stream %dx%d T=%d" % (ny, nx, T))
         got = _run_fp32(u, v, phi, disks, T=T, rows=rdc.RDC_TILE_STREAM, nsteps=(25, 18))
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), T
+
+
+@pytest.mark.parametrize("ny,nx", [(700, 1000), (97, 610), (1500, 250), (2049, 515)])
+def test_fp64_row_pipelines_across_strips_and_segments_equal_the_oracle(ny, nx):
+    """The FP64 row-pipeline kernel (128-column strips) on grids of several
+    strips and many row segments: bit-identical to the oracle for every T it
+    takes."""
+    u, v, phi = inputs.random_state(nx, ny, seed=nx + 5 * ny, umax=0.02, vmax=0.02)
+    disks = [(nx // 2, ny // 2, 4), (3, 5, 3), (nx - 2, ny - 3, 5), (nx // 3, 1, 2)]
+    run = oracle.Run(u, v, phi, inputs.PARAMS_WORKLOAD)
+    run.stimulate(disks)
+    run.advance(25)
+    run.stimulate(disks[:3])
+    run.advance(18)
+    assert np.isfinite(run.u).all()
+    for T in range(2, 9):
+        print_case("fp64 stream %dx%d T=%d" % (ny, nx, T))
+        got = _run_fp32(u, v, phi, disks, T=T, rows=rdc.RDC_TILE_STREAM, nsteps=(25, 18),
+                        dtype="fp64")
+        assert np.array_equal(got[0], run.u) and np.array_equal(got[1], run.v), T
 
 
 # ------------------------------------------------------------------ stimulation, flags, resume
