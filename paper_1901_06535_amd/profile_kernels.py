@@ -72,6 +72,9 @@ def _short(name: str) -> str:
     m = re.match(r"k_stream<(\d+)>", n)
     if m:
         return "k_stream<T=%s>" % m.group(1)
+    m = re.match(r"k_stream64<(\d+)>", n)
+    if m:
+        return "k_stream64<T=%s>" % m.group(1)
     m = re.match(r"k_step1<(\w+), (\w+)>", n)
     if m:
         return "k_step1<%s%s>" % (m.group(1), ",arrival" if m.group(2) == "true" else "")
@@ -125,6 +128,9 @@ def traffic_key(kernel: str, grid: int):
     m = re.match(r"k_stream<T=(\d+)>$", kernel)
     if m:
         return "stream_T%s_%dx%d" % (m.group(1), grid, grid)
+    m = re.match(r"k_stream64<T=(\d+)>$", kernel)
+    if m:
+        return "stream64_T%s_%dx%d" % (m.group(1), grid, grid)
     m = re.match(r"k_stepT64<T=(\d+),rows=(\d+)>$", kernel)
     if m:
         return "stepT64_T%s_r%s_%dx%d" % (m.group(1), m.group(2), grid, grid)
@@ -166,7 +172,7 @@ def summarize(fetch_csv: str, write_csv: str, out_json: str, workload: str) -> N
 TILE_CANDIDATES = [(T, r) for T in (4, 6, 8, 9, 10, 11, 12) for r in (48, 56, 64, 80)]
 STREAM_CANDIDATES = (4, 6, 8, 9, 10, 11)
 UNIFORM_TILES = [(8, 56), (8, 64), (10, 64), (11, 64), (12, 64)]
-CANDIDATES64 = [(8, 56), (8, 64)]
+CANDIDATES64 = [(8, 56), (8, 64), (8, 1)]
 LAUNCHES = 4
 
 
@@ -229,7 +235,8 @@ def main():
             b64.set_block(T)
             b64.set_tile_rows(rows)
             b64.step(LAUNCHES * T)
-            log.append({"kernel": "k_stepT64<T=%d,rows=%d>" % (T, rows), "grid": grid,
+            log.append({"kernel": ("k_stream64<T=%d>" % T) if rows == 1 else
+                        "k_stepT64<T=%d,rows=%d>" % (T, rows), "grid": grid,
                         "launches": LAUNCHES})
         b64.synchronize()
         b64.close()
