@@ -46,7 +46,8 @@ import numpy as np
 from . import inputs, rdc
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STEPPER_SOURCES = ("cell.h", "tile.h", "kernels.h", "kernels.hip", "stream.hip", "tiles_impl.h")
+STEPPER_SOURCES = ("cell.h", "tile.h", "kernels.h", "kernels.hip", "stream.hip", "stream64.hip",
+                   "tiles_impl.h")
 
 
 def source_hash() -> str:
