@@ -304,9 +304,12 @@ rdc_status run_launches(rdc_batch* b, const std::vector<int>& ks, int64_t n, hip
     const int end = tiled ? start ^ static_cast<int>(ks.size() & 1) : start;
     const bool res = b->nres > 0 && n > 0;
     hipError_t e = hipSuccess;
+    const char* what = nullptr;
+    bool forked = false;
     if (res) {
         e = hipEventRecord(b->ev_fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+        forked = e == hipSuccess;
         for (int64_t done = 0; e == hipSuccess && done < n;) {
             const int k = static_cast<int>(std::min<int64_t>(n - done, rdc::kResMaxSteps));
             const int from = done == 0 ? start : end;
@@ -324,25 +327,38 @@ rdc_status run_launches(rdc_batch* b, const std::vector<int>& ks, int64_t n, hip
             e = rdc::launch_resident(a, b->side);
             done += k;
         }
-        if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
-        if (e != hipSuccess) return bhip(b, e, "whole-grid launch");
+        if (forked) {
+            const hipError_t ej = hipEventRecord(b->ev_join, b->side);
+            if (e == hipSuccess) e = ej;
+        }
+        if (e != hipSuccess) what = "whole-grid launch";
     }
-    if (tiled) {
+    rdc_status st = RDC_OK;
+    if (tiled && e == hipSuccess) {
         for (const int k : ks) {
             const rdc::Item* items = nullptr;
             int cnt = 0;
-            rdc_status st = items_for(b, k, b->rows, &items, &cnt);
-            if (st != RDC_OK) return st;
+            st = items_for(b, k, b->rows, &items, &cnt);
+            if (st != RDC_OK) break;
             e = rdc::batch_launch_any(batch_args(b, items, cnt), k, b->rows, s);
-            if (e != hipSuccess) return bhip(b, e, "batched step launch");
+            if (e != hipSuccess) {
+                what = "batched step launch";
+                break;
+            }
             b->cur ^= 1;
         }
     }
-    if (res) {
-        e = hipStreamWaitEvent(s, b->ev_join, 0);
-        if (e != hipSuccess) return bhip(b, e, "whole-grid join");
+    // The side stream is joined back whatever failed, so it never stays
+    // forked (a capture would not end otherwise).
+    if (forked) {
+        const hipError_t ej = hipStreamWaitEvent(s, b->ev_join, 0);
+        if (e == hipSuccess && st == RDC_OK && ej != hipSuccess) {
+            e = ej;
+            what = "whole-grid join";
+        }
     }
-    return RDC_OK;
+    if (e != hipSuccess) return bhip(b, e, what ? what : "whole-grid fork");
+    return st;
 }
 
 // Which grids the whole-grid kernel takes (nx * ny <= max_cells and a shape
