@@ -72,12 +72,25 @@ struct Lane {
     int xb[4];       // byte offsets of its 4 columns, mirrored at the domain edges
     int so[4];       // byte offsets of its 4 output cells, or kOff where not stored
     int so4;         // byte offset of its 16-byte output word, or kOff
+    bool rev;        // (kMirror) its 4 cells are a 16-byte block in reverse order
     uint64_t out;    // lanes holding output cells
 };
 
-template <int T, bool EDGE>
+// How a strip reads its columns:
+//   kInterior  the strip lies inside the grid: one 16-byte word per lane;
+//   kCells     it reaches past an edge: cell by cell, each column mirrored;
+//   kMirror    any strip of a grid whose width is a multiple of 4 (and at
+//              least 256): one 16-byte word per lane, which past an edge is
+//              the mirrored block of 4 columns, taken in reverse order once a
+//              row enters the levels (by the waves of edge strips only).
+// kMirror keeps one copy of the loop in the kernel for every strip.
+enum StripMode { kInterior = 0, kCells = 1, kMirror = 2 };
+
+template <int T, int MODE>
 __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const Lane& ln,
-                                                int y0, int y1, float4 (&phs)[kPhiRows][64]) {
+                                                int y0, int y1, float4 (&phs)[kPhiRows][64],
+                                                bool edge_wave) {
+    constexpr bool EDGE = MODE == kCells;
     const int ny = a.ny;
     const int lane = threadIdx.x & 63;
     const int64_t P = a.pitch;
@@ -130,12 +143,27 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
         }
     };
 
+    // kMirror: a mirrored block as loaded holds this lane's 4 cells in
+    // reverse order; it is put right when the row is first used (the load
+    // then has to be complete anyway), by the waves of edge strips only.
+    auto unmirror = [&](float (&x)[4]) __attribute__((always_inline)) {
+        if (MODE == kMirror && edge_wave) {
+            const float x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+            x[0] = ln.rev ? x3 : x0;
+            x[1] = ln.rev ? x2 : x1;
+            x[2] = ln.rev ? x1 : x2;
+            x[3] = ln.rev ? x0 : x3;
+        }
+    };
+
     // Rows the first ticks need: u^0 rows i0-1 .. i0+kAhead, v and phi rows
     // i0 .. i0+kAhead (relative row j: u^0 slot j mod 6, staging j mod 3).
     load_row(i0 - 1, u0[md(-1, kU0Slots)], vs[md(-1, kStage)], ps[md(-1, kStage)], false);
 #pragma unroll
     for (int j = 0; j <= kAhead; ++j)
         load_row(i0 + j, u0[md(j, kU0Slots)], vs[md(j, kStage)], ps[md(j, kStage)], true);
+    unmirror(u0[md(-1, kU0Slots)]);          // the first tick's north and centre rows
+    unmirror(u0[md(0, kU0Slots)]);
 
     uint64_t bad = 0;
     for (int ib = i0; ib < i_end; ib += kUnroll) {
@@ -145,6 +173,9 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
             // Row i enters level 1: its v moves to its row slot (which held
             // row i - 12, done with since level T took it), its phi is
             // scaled once and kept in the wave's LDS ring for the levels.
+            unmirror(vs[md(s, kStage)]);
+            unmirror(ps[md(s, kStage)]);
+            unmirror(u0[md(s + 1, kU0Slots)]);       // row i + 1: level 1's south from now on
             float cp[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -230,7 +261,7 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
     }
 }
 
-template <int T>
+template <int T, bool MIRROR>
 __global__ __launch_bounds__(kStreamWaves * 64, 2)
 void k_stream(StepArgs<float> a, StreamGeom g) {
     static_assert(stream_fits<T>(), "T too large for the row slots");
@@ -255,6 +286,19 @@ void k_stream(StepArgs<float> a, StreamGeom g) {
     ln.gx = x_load0 + 4 * lane;
 #pragma unroll
     for (int c = 0; c < 4; ++c) ln.xb[c] = 4 * reflect_index(ln.gx + c, nx);
+    ln.rev = false;
+    if (MIRROR) {
+        // Width a multiple of 4 and >= 256: a lane's 4 columns are all
+        // inside or all past one edge, and their mirror images are the 4
+        // columns of one block, in reverse order.
+        if (ln.gx < 0) {
+            ln.xb[0] = 4 * (-4 - ln.gx);
+            ln.rev = true;
+        } else if (ln.gx >= nx) {
+            ln.xb[0] = 4 * (2 * nx - 4 - ln.gx);
+            ln.rev = true;
+        }
+    }
     const bool out_lane = lane >= HX / 4 && lane < (HX + g.bx) / 4 && ln.gx < nx;
     ln.so4 = out_lane ? 4 * ln.gx : kOff;
 #pragma unroll
@@ -263,12 +307,17 @@ void k_stream(StepArgs<float> a, StreamGeom g) {
 
     const int y0 = seg * g.seg_rows;
     const int y1 = min(y0 + g.seg_rows, a.ny);   // output rows [y0, y1)
-    // Interior strips load and store 16-byte words; a strip that reaches
-    // past the left or right edge goes cell by cell.
-    if (x_load0 >= 0 && x_load0 + 256 <= nx)
-        stream_pipeline<T, false>(a, ln, y0, y1, phs[wave]);
-    else
-        stream_pipeline<T, true>(a, ln, y0, y1, phs[wave]);
+    const bool inside = x_load0 >= 0 && x_load0 + 256 <= nx;
+    if (MIRROR) {
+        stream_pipeline<T, kMirror>(a, ln, y0, y1, phs[wave], !inside);
+    } else {
+        // Interior strips load and store 16-byte words; a strip that reaches
+        // past the left or right edge goes cell by cell.
+        if (inside)
+            stream_pipeline<T, kInterior>(a, ln, y0, y1, phs[wave], false);
+        else
+            stream_pipeline<T, kCells>(a, ln, y0, y1, phs[wave], true);
+    }
 }
 
 template <int T>
@@ -279,7 +328,10 @@ hipError_t stream_impl(const StepArgs<float>& a, hipStream_t s) {
     constexpr int bx = (256 - HX - T) & ~3;
     const StreamGeom g = stream_geom(a.nx, a.ny, T, bx, stream_slots());
     const dim3 grid(8 * g.per_xcd), block(kStreamWaves * 64);
-    hipLaunchKernelGGL((k_stream<T>), grid, block, 0, s, a, g);
+    if (a.nx % 4 == 0 && a.nx >= 256)
+        hipLaunchKernelGGL((k_stream<T, true>), grid, block, 0, s, a, g);
+    else
+        hipLaunchKernelGGL((k_stream<T, false>), grid, block, 0, s, a, g);
     return hipGetLastError();
 }
 

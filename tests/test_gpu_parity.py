@@ -202,12 +202,14 @@ def test_small_and_ragged_grids_fp32_launch_shapes(ny, nx):
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (T, rows)
 
 
-@pytest.mark.parametrize("ny,nx", [(700, 1000), (97, 1210), (1500, 250), (2049, 515)])
+@pytest.mark.parametrize("ny,nx", [(700, 1000), (97, 1210), (1500, 250), (2049, 515),
+                                   (333, 1028), (97, 256)])
 def test_row_pipelines_across_strips_and_segments_bitwise(ny, nx):
     """The row-pipeline kernel on grids of several 256-column strips (inner
-    strips with 16-byte accesses, edge strips cell by cell, a ragged last
-    strip) and many row segments: bit-identical to the one-step kernel for
-    every T it takes."""
+    strips with 16-byte accesses; edge strips cell by cell, or, for widths
+    that are multiples of 4 from 256 on, by mirrored 16-byte blocks; a ragged
+    last strip) and many row segments: bit-identical to the one-step kernel
+    for every T it takes."""
     u, v, phi = inputs.random_state(nx, ny, seed=nx + 7 * ny, umax=0.02, vmax=0.02)
     disks = [(nx // 2, ny // 2, 4), (3, 5, 3), (nx - 2, ny - 3, 5), (nx // 3, 1, 2)]
     ref = _run_fp32(u, v, phi, disks, T=1, rows=0, nsteps=(25, 18))
