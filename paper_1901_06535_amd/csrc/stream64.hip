@@ -50,12 +50,20 @@ struct Lane64 {
     int xb[2];       // byte offsets of its 2 columns, mirrored at the domain edges
     int so[2];       // byte offsets of its 2 output cells, or kOff where not stored
     int so2;         // byte offset of its 16-byte output word, or kOff
+    bool rev;        // (kMirror) its 2 cells are a 16-byte block in reverse order
     uint64_t out;    // lanes holding output cells
 };
 
-template <int T, bool EDGE>
+// How a strip reads its columns (as in stream.hip): kInterior, kCells (cell
+// by cell past an edge), or kMirror (even widths from 128 on: 16-byte words
+// everywhere, mirrored blocks past an edge reversed on first use).
+enum StripMode { kInterior = 0, kCells = 1, kMirror = 2 };
+
+template <int T, int MODE>
 __device__ __forceinline__ void pipeline64(const StepArgs<double>& a, const Lane64& ln, int y0,
-                                           int y1, double2 (&phs)[kPhiRows][64]) {
+                                           int y1, double2 (&phs)[kPhiRows][64],
+                                           bool edge_wave) {
+    constexpr bool EDGE = MODE == kCells;
     const int ny = a.ny;
     const int lane = threadIdx.x & 63;
     const int64_t P = a.pitch;
@@ -105,10 +113,22 @@ __device__ __forceinline__ void pipeline64(const StepArgs<double>& a, const Lane
         }
     };
 
+    // kMirror: put a mirrored block's 2 cells in order when the row is
+    // first used (edge strips only).
+    auto unmirror = [&](double (&x)[2]) __attribute__((always_inline)) {
+        if (MODE == kMirror && edge_wave) {
+            const double x0 = x[0], x1 = x[1];
+            x[0] = ln.rev ? x1 : x0;
+            x[1] = ln.rev ? x0 : x1;
+        }
+    };
+
     load_row(i0 - 1, u0[md(-1, kU0Slots)], vs[md(-1, kStage)], ps[md(-1, kStage)], false);
 #pragma unroll
     for (int j = 0; j <= kAhead; ++j)
         load_row(i0 + j, u0[md(j, kU0Slots)], vs[md(j, kStage)], ps[md(j, kStage)], true);
+    unmirror(u0[md(-1, kU0Slots)]);
+    unmirror(u0[md(0, kU0Slots)]);
 
     uint64_t bad = 0;
     for (int ib = i0; ib < i_end; ib += kUnroll) {
@@ -116,6 +136,9 @@ __device__ __forceinline__ void pipeline64(const StepArgs<double>& a, const Lane
         for (int s = 0; s < kUnroll; ++s) {
             const int i = ib + s;
             // Row i enters level 1: v to its row slot, phi to the LDS ring.
+            unmirror(vs[md(s, kStage)]);
+            unmirror(ps[md(s, kStage)]);
+            unmirror(u0[md(s + 1, kU0Slots)]);       // row i + 1: level 1's south from now on
             double pc1[2];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -193,7 +216,7 @@ __device__ __forceinline__ void pipeline64(const StepArgs<double>& a, const Lane
     }
 }
 
-template <int T>
+template <int T, bool MIRROR>
 __global__ __launch_bounds__(kWaves * 64, 2)
 void k_stream64(StepArgs<double> a, StreamGeom g) {
     static_assert(fits64<T>(), "T too large for the row slots");
@@ -215,6 +238,18 @@ void k_stream64(StepArgs<double> a, StreamGeom g) {
     ln.gx = x_load0 + 2 * lane;
 #pragma unroll
     for (int c = 0; c < 2; ++c) ln.xb[c] = 8 * reflect_index(ln.gx + c, nx);
+    ln.rev = false;
+    if (MIRROR) {
+        // Even width >= 128: a lane's 2 columns are both inside or both past
+        // one edge, and their mirror images form one block, reversed.
+        if (ln.gx < 0) {
+            ln.xb[0] = 8 * (-2 - ln.gx);
+            ln.rev = true;
+        } else if (ln.gx >= nx) {
+            ln.xb[0] = 8 * (2 * nx - 2 - ln.gx);
+            ln.rev = true;
+        }
+    }
     const bool out_lane = lane >= HX / 2 && lane < (HX + g.bx) / 2 && ln.gx < nx;
     ln.so2 = out_lane ? 8 * ln.gx : kOff;
 #pragma unroll
@@ -222,10 +257,13 @@ void k_stream64(StepArgs<double> a, StreamGeom g) {
     ln.out = __builtin_amdgcn_ballot_w64(out_lane);
     const int y0 = seg * g.seg_rows;
     const int y1 = min(y0 + g.seg_rows, a.ny);   // output rows [y0, y1)
-    if (x_load0 >= 0 && x_load0 + 128 <= nx)
-        pipeline64<T, false>(a, ln, y0, y1, phs[wave]);
+    const bool inside = x_load0 >= 0 && x_load0 + 128 <= nx;
+    if (MIRROR)
+        pipeline64<T, kMirror>(a, ln, y0, y1, phs[wave], !inside);
+    else if (inside)
+        pipeline64<T, kInterior>(a, ln, y0, y1, phs[wave], false);
     else
-        pipeline64<T, true>(a, ln, y0, y1, phs[wave]);
+        pipeline64<T, kCells>(a, ln, y0, y1, phs[wave], true);
 }
 
 template <int T>
@@ -236,7 +274,10 @@ hipError_t impl64(const StepArgs<double>& a, hipStream_t s) {
     constexpr int bx = (128 - HX - T) & ~1;
     const StreamGeom g = stream_geom(a.nx, a.ny, T, bx, stream_slots());
     const dim3 grid(8 * g.per_xcd), block(kWaves * 64);
-    hipLaunchKernelGGL((k_stream64<T>), grid, block, 0, s, a, g);
+    if (a.nx % 2 == 0 && a.nx >= 128)
+        hipLaunchKernelGGL((k_stream64<T, true>), grid, block, 0, s, a, g);
+    else
+        hipLaunchKernelGGL((k_stream64<T, false>), grid, block, 0, s, a, g);
     return hipGetLastError();
 }
 
