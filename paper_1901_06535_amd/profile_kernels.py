@@ -70,10 +70,10 @@ def _short(name: str) -> str:
     if m:
         return "k_stepT<T=%s,rows=%d%s>" % (m.group(1), 8 * int(m.group(2)),
                                            ",arrival" if m.group(3) == "true" else "")
-    m = re.match(r"k_stream<(\d+)>", n)
+    m = re.match(r"k_stream<(\d+)(, \w+)?>", n)
     if m:
         return "k_stream<T=%s>" % m.group(1)
-    m = re.match(r"k_stream64<(\d+)>", n)
+    m = re.match(r"k_stream64<(\d+)(, \w+)?>", n)
     if m:
         return "k_stream64<T=%s>" % m.group(1)
     m = re.match(r"k_step1<(\w+), (\w+)>", n)
