@@ -227,13 +227,17 @@ def bench_plain(args):
         one_run()
     torch.cuda.synchronize()
     e0, e1 = _events()
+    marks = [_events()[0] for _ in range(args.steps + 1)]   # per-run boundaries
     t_wall = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for k in range(args.steps):
         one_run()
+        marks[k + 1].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
+    run_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
     t = e0.elapsed_time(e1) / 1e3
     cells = wl.nx * wl.ny
     updates = cells * wl.steps * args.steps
@@ -285,6 +289,10 @@ def bench_plain(args):
         "roofline_other": other,
         "one_step_kernel": one_step,
         "tuning_us_per_step": tune,
+        "run_ms": {"median": round(run_ms[len(run_ms) // 2], 3), "min": round(run_ms[0], 3),
+                   "max": round(run_ms[-1], 3),
+                   "median_value": round(cells * wl.steps / (run_ms[len(run_ms) // 2] / 1e3) / 1e9,
+                                         2)},
         "wall_s": round(wall, 3),
     }
     sim.close()
