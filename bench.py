@@ -481,7 +481,9 @@ def bench_variants(args):
     zeros = torch.zeros((wl.ny, wl.nx), dtype=torch.float32, device="cuda")
     disks = [(s.cx, s.cy, s.r) for s in wl.stimuli]
     res = {}
-    for T, rows in ((1, 0), (8, 48), (8, 56), (8, 64), (10, 64), (11, 64), (12, 56), (12, 64)):
+    for T, rows in ((1, 0), (8, 48), (8, 56), (8, 64), (10, 64), (11, 64), (12, 56), (12, 64),
+                    (8, rdc.RDC_TILE_STREAM), (10, rdc.RDC_TILE_STREAM),
+                    (11, rdc.RDC_TILE_STREAM)):
         sim.set_block(T)
         if rows:
             sim.set_tile_rows(rows)
@@ -497,13 +499,15 @@ def bench_variants(args):
         res["T%d_r%d" % (T, rows)] = wl.nx * wl.ny * wl.steps / t / 1e9
     sim.close()
     # The FP64 variants on the same inputs: one step per launch (40 B per
-    # cell-update, HBM-bound) and T steps per launch on 128-column tiles.
+    # cell-update, HBM-bound), T steps per launch on 128-column tiles, and
+    # the FP64 row pipelines (rows 1).
     s64 = rdc.Sim(wl.nx, wl.ny, wl.params, "fp64")
     s64.set_phi(wl.phi)
     z64 = torch.zeros((wl.ny, wl.nx), dtype=torch.float64, device="cuda")
     n64 = 480
     res64 = {}
-    for T, rows in ((1, 0), (4, 56), (6, 56), (8, 48), (8, 56), (8, 64)):
+    for T, rows in ((1, 0), (4, 56), (6, 56), (8, 48), (8, 56), (8, 64),
+                    (6, rdc.RDC_TILE_STREAM), (8, rdc.RDC_TILE_STREAM)):
         s64.set_block(T)
         s64.set_tile_rows(rows)
         s64.write(z64, z64)
