@@ -101,12 +101,13 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
     Consts<float> k = a.k;
     k.k0 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(k.k0), 0xe4, 0xf, 0xf, false));
 
-    // Every level runs on every tick, also before its first row and after
-    // its last (levels t and t+1 start and stop together apart from one row
-    // at either end, so such a row of u^t is never read by level t+1, and a
-    // row's v is not touched by any level after it left the range of rows
-    // that level owns); only level T's output is checked and written, and
-    // only where it ran on a row of the segment.  Slots start at zero.
+    // Every level runs on every tick from its first row on, also after its
+    // last (levels t and t+1 stop together apart from one row, so such a row
+    // of u^t is never read by level t+1, and a row's v is not touched by any
+    // level after it left the range of rows that level owns); only level
+    // T's output is checked and written, and only where it ran on a row of
+    // the segment.  Slots start at zero.
+    constexpr int kRampBodies = (2 * T - 2 + kUnroll - 1) / kUnroll;
     float u0[kU0Slots][4] = {};                // u^0 rows (level 1's window)
     float uw[T + 1][3][4] = {};                // uw[t]: rows of u^(t-1), t >= 2
     float vr[kRowSlots][4] = {};               // v of the rows in the levels
@@ -166,94 +167,135 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
     unmirror(u0[md(0, kU0Slots)]);
 
     uint64_t bad = 0;
-    for (int ib = i0; ib < i_end; ib += kUnroll) {
+    // One tick: row i enters level 1.  s is the tick's place in the unrolled
+    // body and fixes every slot.  ramp >= 0 in the first bodies a wave walks
+    // (the body's first tick counted from i0): there level t has no row of
+    // its range before tick i0 + 2t - 2 and is left out, which the compiler
+    // settles, since ramp and s are constants once the bodies are unrolled.
+    // ramp = -1 in the loop after them, where every level runs.
+    auto tick = [&](const int i, const int s, const int ramp) __attribute__((always_inline)) {
+        // Row i enters level 1: its v moves to its row slot (which held
+        // row i - 12, done with since level T took it), its phi is
+        // scaled once and kept in the wave's LDS ring for the levels.
+        unmirror(vs[md(s, kStage)]);
+        unmirror(ps[md(s, kStage)]);
+        unmirror(u0[md(s + 1, kU0Slots)]);       // row i + 1: level 1's south from now on
+        float cp[4];
 #pragma unroll
-        for (int s = 0; s < kUnroll; ++s) {
-            const int i = ib + s;
-            // Row i enters level 1: its v moves to its row slot (which held
-            // row i - 12, done with since level T took it), its phi is
-            // scaled once and kept in the wave's LDS ring for the levels.
-            unmirror(vs[md(s, kStage)]);
-            unmirror(ps[md(s, kStage)]);
-            unmirror(u0[md(s + 1, kU0Slots)]);       // row i + 1: level 1's south from now on
-            float cp[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                vr[md(s, kRowSlots)][c] = vs[md(s, kStage)][c];
-                cp[c] = scaled_phi(ps[md(s, kStage)][c], k);
-            }
-            phs[i & (kPhiRows - 1)][lane] = make_float4(cp[0], cp[1], cp[2], cp[3]);
-            // The row first needed kAhead ticks from now.  Its slots held row
-            // i + 1 + kAhead - 6 (u^0) and - 3 (staging), both done with.
-            load_row(i + 1 + kAhead, u0[md(s + 1 + kAhead, kU0Slots)],
-                     vs[md(s + 1 + kAhead, kStage)], ps[md(s + 1 + kAhead, kStage)], true);
+        for (int c = 0; c < 4; ++c) {
+            vr[md(s, kRowSlots)][c] = vs[md(s, kStage)][c];
+            cp[c] = scaled_phi(ps[md(s, kStage)][c], k);
+        }
+        phs[i & (kPhiRows - 1)][lane] = make_float4(cp[0], cp[1], cp[2], cp[3]);
+        // The row first needed kAhead ticks from now.  Its slots held row
+        // i + 1 + kAhead - 6 (u^0) and - 3 (staging), both done with.
+        load_row(i + 1 + kAhead, u0[md(s + 1 + kAhead, kU0Slots)],
+                 vs[md(s + 1 + kAhead, kStage)], ps[md(s + 1 + kAhead, kStage)], true);
 
-            float un[4];
-            // level T runs on a row of the segment (uniform)
-            const bool live_T = i >= i0 + 2 * T - 2 && i < i_end;
+        float un[4];
+        // level T runs on a row of the segment (uniform)
+        const bool live_T = i >= i0 + 2 * T - 2 && i < i_end;
 #pragma unroll
-            for (int t = 1; t <= T; ++t) {
-                const int rs = md(s - t + 1, kRowSlots);           // slot of row rho = i - t + 1
-                const float* n;
-                const float* c;
-                const float* so;
-                if (t == 1) {
-                    n = u0[md(s - 1, kU0Slots)];
-                    c = u0[md(s, kU0Slots)];
-                    so = u0[md(s + 1, kU0Slots)];
-                } else {
-                    n = uw[t][md(s - t, 3)];
-                    c = uw[t][md(s - t + 1, 3)];
-                    so = uw[t][md(s - t + 2, 3)];
-                }
-                float pc[4];
-                if (t == 1) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) pc[e] = cp[e];
-                } else {
-                    const float4 q = phs[(i - t + 1) & (kPhiRows - 1)][lane];
-                    pc[0] = q.x; pc[1] = q.y; pc[2] = q.z; pc[3] = q.w;
-                }
-                const float west = from_west_lane(c[3]);
-                const float east = from_east_lane(c[0]);
-                // (west and east enter as a sum; the lane-shifted value goes
-                // first so the shift folds into the add)
-                cell_update(c[0], c[1], west, n[0], so[0], vr[rs][0], pc[0], k, un[0],
-                            vr[rs][0]);
-                cell_update(c[1], c[0], c[2], n[1], so[1], vr[rs][1], pc[1], k, un[1],
-                            vr[rs][1]);
-                cell_update(c[2], c[1], c[3], n[2], so[2], vr[rs][2], pc[2], k, un[2],
-                            vr[rs][2]);
-                cell_update(c[3], c[2], east, n[3], so[3], vr[rs][3], pc[3], k, un[3],
-                            vr[rs][3]);
-                if (t < T) {
-                    // row rho of u^t: level t+1's newest row
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) uw[t < T ? t + 1 : T][md(s - t + 1, 3)][e] = un[e];
-                } else if (live_T) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const bool ok = __builtin_isfinite(un[e]) && __builtin_isfinite(vr[rs][e]);
-                        bad |= __builtin_amdgcn_ballot_w64(!ok);
-                    }
-                }
-            }
-            // Row i - T + 1 of u^T and v^T, written where level T ran on it.
-            const int rs = md(s - T + 1, kRowSlots);
-            const int64_t off = (int64_t)min(max(i - T + 1, 0), ny - 1) * P;
-            const int nb = live_T ? row_bytes : 0;
-            const auto ro = row_rsrc(a.u_out + off, nb);
-            const auto rv = row_rsrc(a.v_out + off, nb);
-            if (!EDGE) {
-                buf_store4(ro, ln.so4, un[0], un[1], un[2], un[3]);
-                buf_store4(rv, ln.so4, vr[rs][0], vr[rs][1], vr[rs][2], vr[rs][3]);
+        for (int t = 1; t <= T; ++t) {
+            if (ramp >= 0 && ramp + s < 2 * t - 2) continue;   // no row of level t yet
+            const int rs = md(s - t + 1, kRowSlots);           // slot of row rho = i - t + 1
+            const float* n;
+            const float* c;
+            const float* so;
+            if (t == 1) {
+                n = u0[md(s - 1, kU0Slots)];
+                c = u0[md(s, kU0Slots)];
+                so = u0[md(s + 1, kU0Slots)];
             } else {
+                n = uw[t][md(s - t, 3)];
+                c = uw[t][md(s - t + 1, 3)];
+                so = uw[t][md(s - t + 2, 3)];
+            }
+            float pc[4];
+            if (t == 1) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) pc[e] = cp[e];
+            } else {
+                const float4 q = phs[(i - t + 1) & (kPhiRows - 1)][lane];
+                pc[0] = q.x; pc[1] = q.y; pc[2] = q.z; pc[3] = q.w;
+            }
+            const float west = from_west_lane(c[3]);
+            const float east = from_east_lane(c[0]);
+            // (west and east enter as a sum; the lane-shifted value goes
+            // first so the shift folds into the add)
+            cell_update(c[0], c[1], west, n[0], so[0], vr[rs][0], pc[0], k, un[0],
+                        vr[rs][0]);
+            cell_update(c[1], c[0], c[2], n[1], so[1], vr[rs][1], pc[1], k, un[1],
+                        vr[rs][1]);
+            cell_update(c[2], c[1], c[3], n[2], so[2], vr[rs][2], pc[2], k, un[2],
+                        vr[rs][2]);
+            cell_update(c[3], c[2], east, n[3], so[3], vr[rs][3], pc[3], k, un[3],
+                        vr[rs][3]);
+            if (ramp >= 0) {
+                // In the ramp bodies (straight-line code) the compiler would
+                // otherwise sink a level's work to the tick where its results
+                // are first read, holding the rows it reads live meanwhile.
+#pragma unroll
+                for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(un[e]), "+v"(vr[rs][e]));
+            }
+            if (t < T) {
+                // row rho of u^t: level t+1's newest row
+#pragma unroll
+                for (int e = 0; e < 4; ++e) uw[t < T ? t + 1 : T][md(s - t + 1, 3)][e] = un[e];
+            } else if (live_T) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    buf_store1(ro, ln.so[e], un[e]);
-                    buf_store1(rv, ln.so[e], vr[rs][e]);
+                    const bool ok = __builtin_isfinite(un[e]) && __builtin_isfinite(vr[rs][e]);
+                    bad |= __builtin_amdgcn_ballot_w64(!ok);
                 }
             }
+        }
+        // Row i - T + 1 of u^T and v^T, written where level T ran on it.
+        if (ramp >= 0 && ramp + s < 2 * T - 2) return;
+        const int rs = md(s - T + 1, kRowSlots);
+        const int64_t off = (int64_t)min(max(i - T + 1, 0), ny - 1) * P;
+        const int nb = live_T ? row_bytes : 0;
+        const auto ro = row_rsrc(a.u_out + off, nb);
+        const auto rv = row_rsrc(a.v_out + off, nb);
+        if (!EDGE) {
+            buf_store4(ro, ln.so4, un[0], un[1], un[2], un[3]);
+            buf_store4(rv, ln.so4, vr[rs][0], vr[rs][1], vr[rs][2], vr[rs][3]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                buf_store1(ro, ln.so[e], un[e]);
+                buf_store1(rv, ln.so[e], vr[rs][e]);
+            }
+        }
+    };
+    // A wave walks at least 2T - 1 ticks, so it always walks the ramp
+    // bodies (as before, ticks past i_end load and store nothing).  Each is
+    // written out: unrolling a loop over them would exceed the compiler's
+    // limit for forced unrolling and leave `ramp` a run-time value.
+    auto ramp_body = [&](const int r0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+            tick(i0 + r0 + s, s, r0);
+            // keep the scheduler from hoisting later ticks' loads into this
+            // one: in straight-line code it would hold many rows at once
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    static_assert(kRampBodies >= 1 && kRampBodies <= 2, "ramp of at most two loop bodies");
+    ramp_body(0);
+    if constexpr (kRampBodies > 1) ramp_body(kUnroll);
+    // Whole bodies, then the ticks left (fewer than kUnroll) by a copy that
+    // stops after the last: a segment's ticks need not fill whole bodies.
+    int ib = i0 + kRampBodies * kUnroll;
+    for (; ib + kUnroll <= i_end; ib += kUnroll) {
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) tick(ib + s, s, -1);
+    }
+    if (ib < i_end) {
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+            if (s > 0 && ib + s >= i_end) break;
+            tick(ib + s, s, -1);
         }
     }
     if (bad & ln.out) {
@@ -350,9 +392,13 @@ StreamGeom stream_geom(int nx, int ny, int T, int bx, int slots) {
         const int rows = (ny + nseg - 1) / nseg;
         const int64_t items = (int64_t)g.nstrips * ((ny + rows - 1) / rows);
         const int64_t rounds = (items + slots - 1) / slots;
-        // ticks a wave walks: rows + 2T - 2, in whole unrolled loop bodies
-        const int64_t ticks = (rows + 2 * T - 2 + kUnroll - 1) / kUnroll * kUnroll;
-        const double cost = (double)rounds * ticks;
+        // per wave, in level-rows: T levels on each of its rows + 2T - 2
+        // ticks (at least the ramp bodies) less the T(T-1) the ramp leaves
+        // out, about half a level per tick for its loads and stores, and two
+        // ticks for the first rows' load latency
+        const int64_t ticks = max(rows + 2 * T - 2, (2 * T - 2 + kUnroll - 1) / kUnroll * kUnroll);
+        const double cost =
+            (double)rounds * ((T + 0.5) * ticks - (double)T * (T - 1) + 2.0 * T);
         if (best < 0 || cost < best) {
             best = cost;
             best_rows = rows;

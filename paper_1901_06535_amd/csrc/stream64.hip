@@ -72,8 +72,10 @@ __device__ __forceinline__ void pipeline64(const StepArgs<double>& a, const Lane
     const int i_end = y1 + T - 1;              // ticks [i0, i_end)
     const Consts<double> k = a.k;
 
-    // As in the FP32 kernel: every level runs on every tick; only level T's
-    // output is checked and written, where it ran on a row of the segment.
+    // As in the FP32 kernel: every level runs on every tick from its first
+    // row on; only level T's output is checked and written, where it ran on
+    // a row of the segment.
+    constexpr int kRampBodies = (2 * T - 2 + kUnroll - 1) / kUnroll;
     double u0[kU0Slots][2] = {};               // u^0 rows (level 1's window)
     double uw[T + 1][3][2] = {};               // uw[t]: rows of u^(t-1), t >= 2
     double vr[kRowSlots][2] = {};              // v of the rows in the levels
@@ -131,84 +133,111 @@ __device__ __forceinline__ void pipeline64(const StepArgs<double>& a, const Lane
     unmirror(u0[md(0, kU0Slots)]);
 
     uint64_t bad = 0;
-    for (int ib = i0; ib < i_end; ib += kUnroll) {
+    // One tick, as in the FP32 kernel: s fixes the slots; in the ramp bodies
+    // (ramp >= 0, the body's first tick counted from i0) the levels with no
+    // row yet are left out, and their results are kept in place there.
+    auto tick = [&](const int i, const int s, const int ramp) __attribute__((always_inline)) {
+        // Row i enters level 1: v to its row slot, phi to the LDS ring.
+        unmirror(vs[md(s, kStage)]);
+        unmirror(ps[md(s, kStage)]);
+        unmirror(u0[md(s + 1, kU0Slots)]);       // row i + 1: level 1's south from now on
+        double pc1[2];
 #pragma unroll
-        for (int s = 0; s < kUnroll; ++s) {
-            const int i = ib + s;
-            // Row i enters level 1: v to its row slot, phi to the LDS ring.
-            unmirror(vs[md(s, kStage)]);
-            unmirror(ps[md(s, kStage)]);
-            unmirror(u0[md(s + 1, kU0Slots)]);       // row i + 1: level 1's south from now on
-            double pc1[2];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                vr[md(s, kRowSlots)][c] = vs[md(s, kStage)][c];
-                pc1[c] = scaled_phi(ps[md(s, kStage)][c], k);
-            }
-            phs[i & (kPhiRows - 1)][lane] = make_double2(pc1[0], pc1[1]);
-            load_row(i + 1 + kAhead, u0[md(s + 1 + kAhead, kU0Slots)],
-                     vs[md(s + 1 + kAhead, kStage)], ps[md(s + 1 + kAhead, kStage)], true);
+        for (int c = 0; c < 2; ++c) {
+            vr[md(s, kRowSlots)][c] = vs[md(s, kStage)][c];
+            pc1[c] = scaled_phi(ps[md(s, kStage)][c], k);
+        }
+        phs[i & (kPhiRows - 1)][lane] = make_double2(pc1[0], pc1[1]);
+        load_row(i + 1 + kAhead, u0[md(s + 1 + kAhead, kU0Slots)],
+                 vs[md(s + 1 + kAhead, kStage)], ps[md(s + 1 + kAhead, kStage)], true);
 
-            double un[2];
-            const bool live_T = i >= i0 + 2 * T - 2 && i < i_end;
+        double un[2];
+        const bool live_T = i >= i0 + 2 * T - 2 && i < i_end;
 #pragma unroll
-            for (int t = 1; t <= T; ++t) {
-                const int rs = md(s - t + 1, kRowSlots);           // slot of row rho = i - t + 1
-                const double* n;
-                const double* c;
-                const double* so;
-                if (t == 1) {
-                    n = u0[md(s - 1, kU0Slots)];
-                    c = u0[md(s, kU0Slots)];
-                    so = u0[md(s + 1, kU0Slots)];
-                } else {
-                    n = uw[t][md(s - t, 3)];
-                    c = uw[t][md(s - t + 1, 3)];
-                    so = uw[t][md(s - t + 2, 3)];
-                }
-                double pc[2];
-                if (t == 1) {
-                    pc[0] = pc1[0];
-                    pc[1] = pc1[1];
-                } else {
-                    const double2 q = phs[(i - t + 1) & (kPhiRows - 1)][lane];
-                    pc[0] = q.x;
-                    pc[1] = q.y;
-                }
-                const double west = from_west_lane(c[1]);
-                const double east = from_east_lane(c[0]);
-                // west and east enter the update as a sum (either order)
-                cell_update(c[0], west, c[1], n[0], so[0], vr[rs][0], pc[0], k, un[0],
-                            vr[rs][0]);
-                cell_update(c[1], c[0], east, n[1], so[1], vr[rs][1], pc[1], k, un[1],
-                            vr[rs][1]);
-                if (t < T) {
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) uw[t < T ? t + 1 : T][md(s - t + 1, 3)][e] = un[e];
-                } else if (live_T) {
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const bool ok = __builtin_isfinite(un[e]) && __builtin_isfinite(vr[rs][e]);
-                        bad |= __builtin_amdgcn_ballot_w64(!ok);
-                    }
-                }
-            }
-            // Row i - T + 1 of u^T and v^T, written where level T ran on it.
-            const int rs = md(s - T + 1, kRowSlots);
-            const int64_t off = (int64_t)min(max(i - T + 1, 0), ny - 1) * P;
-            const int nb = live_T ? row_bytes : 0;
-            const auto ro = row_rsrc(a.u_out + off, nb);
-            const auto rv = row_rsrc(a.v_out + off, nb);
-            if (!EDGE) {
-                buf_store2d(ro, ln.so2, un[0], un[1]);
-                buf_store2d(rv, ln.so2, vr[rs][0], vr[rs][1]);
+        for (int t = 1; t <= T; ++t) {
+            if (ramp >= 0 && ramp + s < 2 * t - 2) continue;   // no row of level t yet
+            const int rs = md(s - t + 1, kRowSlots);           // slot of row rho = i - t + 1
+            const double* n;
+            const double* c;
+            const double* so;
+            if (t == 1) {
+                n = u0[md(s - 1, kU0Slots)];
+                c = u0[md(s, kU0Slots)];
+                so = u0[md(s + 1, kU0Slots)];
             } else {
+                n = uw[t][md(s - t, 3)];
+                c = uw[t][md(s - t + 1, 3)];
+                so = uw[t][md(s - t + 2, 3)];
+            }
+            double pc[2];
+            if (t == 1) {
+                pc[0] = pc1[0];
+                pc[1] = pc1[1];
+            } else {
+                const double2 q = phs[(i - t + 1) & (kPhiRows - 1)][lane];
+                pc[0] = q.x;
+                pc[1] = q.y;
+            }
+            const double west = from_west_lane(c[1]);
+            const double east = from_east_lane(c[0]);
+            // west and east enter the update as a sum (either order)
+            cell_update(c[0], west, c[1], n[0], so[0], vr[rs][0], pc[0], k, un[0],
+                        vr[rs][0]);
+            cell_update(c[1], c[0], east, n[1], so[1], vr[rs][1], pc[1], k, un[1],
+                        vr[rs][1]);
+            if (ramp >= 0) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) asm volatile("" : "+v"(un[e]), "+v"(vr[rs][e]));
+            }
+            if (t < T) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) uw[t < T ? t + 1 : T][md(s - t + 1, 3)][e] = un[e];
+            } else if (live_T) {
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
-                    buf_store1d(ro, ln.so[e], un[e]);
-                    buf_store1d(rv, ln.so[e], vr[rs][e]);
+                    const bool ok = __builtin_isfinite(un[e]) && __builtin_isfinite(vr[rs][e]);
+                    bad |= __builtin_amdgcn_ballot_w64(!ok);
                 }
             }
+        }
+        // Row i - T + 1 of u^T and v^T, written where level T ran on it.
+        if (ramp >= 0 && ramp + s < 2 * T - 2) return;
+        const int rs = md(s - T + 1, kRowSlots);
+        const int64_t off = (int64_t)min(max(i - T + 1, 0), ny - 1) * P;
+        const int nb = live_T ? row_bytes : 0;
+        const auto ro = row_rsrc(a.u_out + off, nb);
+        const auto rv = row_rsrc(a.v_out + off, nb);
+        if (!EDGE) {
+            buf_store2d(ro, ln.so2, un[0], un[1]);
+            buf_store2d(rv, ln.so2, vr[rs][0], vr[rs][1]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                buf_store1d(ro, ln.so[e], un[e]);
+                buf_store1d(rv, ln.so[e], vr[rs][e]);
+            }
+        }
+    };
+    auto ramp_body = [&](const int r0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+            tick(i0 + r0 + s, s, r0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    static_assert(kRampBodies >= 1 && kRampBodies <= 2, "ramp of at most two loop bodies");
+    ramp_body(0);
+    if constexpr (kRampBodies > 1) ramp_body(kUnroll);
+    int ib = i0 + kRampBodies * kUnroll;
+    for (; ib + kUnroll <= i_end; ib += kUnroll) {
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) tick(ib + s, s, -1);
+    }
+    if (ib < i_end) {
+#pragma unroll
+        for (int s = 0; s < kUnroll; ++s) {
+            if (s > 0 && ib + s >= i_end) break;
+            tick(ib + s, s, -1);
         }
     }
     if (bad & ln.out) {
