@@ -219,16 +219,17 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
                 const float4 q = phs[(i - t + 1) & (kPhiRows - 1)][lane];
                 pc[0] = q.x; pc[1] = q.y; pc[2] = q.z; pc[3] = q.w;
             }
+            // West and east enter the update as a sum.  Each lane shift sits
+            // right before the update that takes it: the compiler folds a
+            // shift into its add only a few instructions away.
             const float west = from_west_lane(c[3]);
-            const float east = from_east_lane(c[0]);
-            // (west and east enter as a sum; the lane-shifted value goes
-            // first so the shift folds into the add)
             cell_update(c[0], c[1], west, n[0], so[0], vr[rs][0], pc[0], k, un[0],
                         vr[rs][0]);
             cell_update(c[1], c[0], c[2], n[1], so[1], vr[rs][1], pc[1], k, un[1],
                         vr[rs][1]);
             cell_update(c[2], c[1], c[3], n[2], so[2], vr[rs][2], pc[2], k, un[2],
                         vr[rs][2]);
+            const float east = from_east_lane(c[0]);
             cell_update(c[3], c[2], east, n[3], so[3], vr[rs][3], pc[3], k, un[3],
                         vr[rs][3]);
             if (ramp >= 0) {

@@ -252,13 +252,14 @@ __device__ __forceinline__ void step_tile(const StepArgs<float>& a, int tx, int 
                 const float4 c = lds[r][lane];
                 const float4 n = lds[r - 1][lane];
                 const float4 s = lds[r + 1][lane];
+                // West and east enter the update as a sum.  Each lane shift
+                // sits right before the update that takes it: the compiler
+                // folds a shift into its add only a few instructions away.
                 const float west = from_west_lane(c.w);
-                const float east = from_east_lane(c.x);
-                // (west and east enter as a sum; the lane-shifted value goes
-                // first so the shift folds into the add)
                 cell_update(c.x, c.y, west, n.x, s.x, vr[k][0], pr[k][0], a.k, un[k][0], vr[k][0]);
                 cell_update(c.y, c.x, c.z, n.y, s.y, vr[k][1], pr[k][1], a.k, un[k][1], vr[k][1]);
                 cell_update(c.z, c.y, c.w, n.z, s.z, vr[k][2], pr[k][2], a.k, un[k][2], vr[k][2]);
+                const float east = from_east_lane(c.x);
                 cell_update(c.w, c.z, east, n.w, s.w, vr[k][3], pr[k][3], a.k, un[k][3], vr[k][3]);
                 if (OUT && r >= T && r < EY - T) {
                     if (a.arrival) {
