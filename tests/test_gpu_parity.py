@@ -220,6 +220,47 @@ def test_row_pipelines_across_strips_and_segments_bitwise(ny, nx):
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), T
 
 
+@pytest.mark.parametrize("nx", [14848, 14846])
+def test_row_pipelines_on_tall_segments_bitwise(nx):
+    """Grids of 60-64 strips and 1024 rows: with a wave per (strip, segment)
+    and 2048 resident waves, segments are 31-32 rows tall, so a wave walks
+    the ramp bodies (where levels with no row yet are left out), whole loop
+    bodies and a partial last one (at T = 2..4 the last segment is a single
+    row: the ramp bodies only).  Each launch is exactly T steps; bit-identical
+    to the one-step kernel for T = 2..11, width a multiple of 4 (mirrored
+    16-byte edge blocks) and not (edge strips cell by cell)."""
+    ny = 1024
+    u, v, phi = inputs.random_state(nx, ny, seed=nx + 3, umax=0.02, vmax=0.02)
+    disks = [(nx // 2, ny // 2, 4), (3, 5, 3), (nx - 2, ny - 3, 5), (nx // 3, 1, 2),
+             (250, 30, 6), (nx - 300, 40, 6)]
+    for T in range(2, 12):
+        print_case("stream tall segments %dx%d T=%d" % (ny, nx, T))
+        ref = _run_fp32(u, v, phi, disks, T=1, rows=0, nsteps=(2 * T, T))
+        assert np.isfinite(ref[0]).all()
+        got = _run_fp32(u, v, phi, disks, T=T, rows=rdc.RDC_TILE_STREAM, nsteps=(2 * T, T))
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), T
+
+
+def test_fp64_row_pipelines_on_tall_segments_equal_the_oracle():
+    """The FP64 row pipelines (128-column strips) on 1024 x 7424: 60-67
+    strips, segments 31-35 rows tall, so waves walk the ramp bodies, whole
+    loop bodies and a partial last one; each launch exactly T steps;
+    bit-identical to the oracle for T = 2..8."""
+    ny, nx = 1024, 7424
+    u, v, phi = inputs.random_state(nx, ny, seed=77, umax=0.02, vmax=0.02)
+    disks = [(nx // 2, ny // 2, 4), (3, 5, 3), (nx - 2, ny - 3, 5), (nx // 3, 1, 2)]
+    for T in range(2, 9):
+        print_case("fp64 stream tall segments %dx%d T=%d" % (ny, nx, T))
+        run = oracle.Run(u, v, phi, inputs.PARAMS_WORKLOAD)
+        run.stimulate(disks)
+        run.advance(2 * T)
+        run.stimulate(disks[:3])
+        run.advance(T)
+        got = _run_fp32(u, v, phi, disks, T=T, rows=rdc.RDC_TILE_STREAM, nsteps=(2 * T, T),
+                        dtype="fp64")
+        assert np.array_equal(got[0], run.u) and np.array_equal(got[1], run.v), T
+
+
 @pytest.mark.parametrize("ny,nx", [(700, 1000), (97, 610), (1500, 250), (2049, 515)])
 def test_fp64_row_pipelines_across_strips_and_segments_equal_the_oracle(ny, nx):
     """The FP64 row-pipeline kernel (128-column strips) on grids of several
