@@ -250,7 +250,11 @@ rdc_status rdc_batch_create(int32_t count, const rdc_sim_desc *sims, const rdc_b
 rdc_status rdc_batch_destroy(rdc_batch *b);
 
 /* Steps per launch (1..12, default 8) and tile rows (48, 56 or 64, default
- * 56) of the batched kernel.  Does not change results. */
+ * 56) of the batched kernel, or rows = RDC_TILE_STREAM with T in 1..11: the
+ * tiled grids then run on row pipelines (one wave per strip of a grid and
+ * segment of its rows, the segment heights planned over all grids so that
+ * every wave's work is about equal; launches of one step take 56-row
+ * tiles).  Does not change results.  RDC_E_INVAL outside these values. */
 rdc_status rdc_batch_set_block(rdc_batch *b, int32_t T, int32_t rows);
 
 /* Whole-grid path for small grids (same scheme, Sec. 2 Eq. (1)): a grid of

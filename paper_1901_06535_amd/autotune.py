@@ -126,7 +126,7 @@ def tune_sim(sim, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = DEFAULT_R
     return rec
 
 
-def tune_batch(batch, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = (48, 56, 64),
+def tune_batch(batch, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = (48, 56, 64, 1),
                launches: int = 24, use_cache: bool = True) -> Dict:
     """Pick (T, rows) for an `rdc.BatchSim` (keyed by its list of grid sizes
     and its whole-grid path setting, which decides the grids that are

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "cell.h"
 
 namespace rdc {
@@ -53,5 +55,42 @@ struct ResArgs {
 bool resident_layout(int nx, int ny, int* m, int* groups);
 
 hipError_t launch_resident(const ResArgs& a, hipStream_t s);
+
+// Row pipelines over many grids (stream.hip): one wave per item, output
+// columns [strip * stream_strip_cols(T), + stream_strip_cols(T)) and output
+// rows [y0, y1) of grid `sim`; 4 waves per workgroup, workgroups dealt to
+// the 8 XCDs in contiguous runs of per_xcd.
+struct StreamItem {
+    int sim, strip, y0, y1;
+};
+
+struct BatchStreamArgs {
+    const float* u;     // pooled planes holding the state on entry
+    const float* v;
+    const float* phi;
+    float* u_out;       // pooled planes receiving it (not u, v)
+    float* v_out;
+    const SimDev* sims;
+    const StreamItem* items;
+    int* flags;         // sticky non-finite flag per grid
+    int nitems;         // work items (waves), >= 1
+    int per_xcd;        // workgroups per XCD: 8 * per_xcd * 4 >= nitems
+};
+
+// Output columns per strip of the row pipelines at T steps per launch
+// (0 outside 2..11).
+int stream_strip_cols(int T);
+hipError_t launch_batch_stream(const BatchStreamArgs& b, int T, hipStream_t s);
+
+// Work items of the row pipelines at T (2..11) steps per launch over grids
+// (batch index, size), `slots` waves resident at a time: every grid's
+// strips, its rows cut into segments of near-equal height, all segments
+// under one bound chosen to keep lowest the longest wave's work times the
+// rounds of resident waves; longest items first.
+struct GridShape {
+    int sim, nx, ny;
+};
+std::vector<StreamItem> batch_stream_items(const std::vector<GridShape>& grids, int T,
+                                           int slots);
 
 }  // namespace rdc

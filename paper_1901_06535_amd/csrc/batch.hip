@@ -161,6 +161,8 @@ struct rdc_batch {
     int* d_flags = nullptr;
     // tile work items of the grids not taken by the resident kernel
     std::map<std::pair<int, int>, std::pair<rdc::Item*, int>> items;  // (T, rows) -> list
+    // their row-pipeline work items (rows == RDC_TILE_STREAM)
+    std::map<int, std::pair<rdc::StreamItem*, int>> sitems;          // T -> list
     // whole-grid LDS path: cell limit, which grids it takes, their items
     int32_t res_max_cells = RDC_BATCH_RESIDENT_DEFAULT;
     std::vector<char> resident;
@@ -274,6 +276,82 @@ rdc::BatchArgs batch_args(const rdc_batch* b, const rdc::Item* items, int n) {
     return a;
 }
 
+// Row-pipeline work items of every tiled grid for T steps per launch
+// (2..11), built once and kept on the device.
+rdc_status stream_items_for(rdc_batch* b, int T, const rdc::StreamItem** out, int* n) {
+    auto it = b->sitems.find(T);
+    if (it == b->sitems.end()) {
+        std::vector<rdc::GridShape> grids;
+        for (int s = 0; s < b->count; ++s)
+            if (!b->resident[s]) grids.push_back({s, b->sims[s].nx, b->sims[s].ny});
+        const std::vector<rdc::StreamItem> list =
+            rdc::batch_stream_items(grids, T, rdc::stream_slots());
+        rdc::StreamItem* d = nullptr;
+        hipError_t e = hipSuccess;
+        if (!list.empty()) e = hipMalloc(&d, sizeof(rdc::StreamItem) * list.size());
+        if (e == hipSuccess && !list.empty())
+            e = hipMemcpy(d, list.data(), sizeof(rdc::StreamItem) * list.size(),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (d) (void)hipFree(d);
+            return bhip(b, e, "row-pipeline work-item table");
+        }
+        it = b->sitems.emplace(T, std::make_pair(d, static_cast<int>(list.size()))).first;
+    }
+    *out = it->second.first;
+    *n = it->second.second;
+    return RDC_OK;
+}
+
+// Whether a launch of k steps runs on the row pipelines (else on tiles).
+bool stream_launch(const rdc_batch* b, int k) {
+    return b->rows == RDC_TILE_STREAM && rdc::stream_supported(k);
+}
+
+// Tile height of the tiled launches (the row pipelines' batches take 56-row
+// tiles for launches the pipelines do not run: one step).
+int tile_rows_of(const rdc_batch* b) { return b->rows == RDC_TILE_STREAM ? 56 : b->rows; }
+
+// Builds the work-item table a launch of k steps needs.
+rdc_status tables_for(rdc_batch* b, int k) {
+    int cnt = 0;
+    if (stream_launch(b, k)) {
+        const rdc::StreamItem* items = nullptr;
+        return stream_items_for(b, k, &items, &cnt);
+    }
+    const rdc::Item* items = nullptr;
+    return items_for(b, k, tile_rows_of(b), &items, &cnt);
+}
+
+// One launch of k steps over the tiled grids, from planes b->cur.
+rdc_status launch_tiled(rdc_batch* b, int k, hipStream_t s, hipError_t* e) {
+    int cnt = 0;
+    if (stream_launch(b, k)) {
+        const rdc::StreamItem* items = nullptr;
+        const rdc_status st = stream_items_for(b, k, &items, &cnt);
+        if (st != RDC_OK) return st;
+        rdc::BatchStreamArgs a;
+        a.u = b->pool[b->cur];
+        a.v = b->pool[2 + b->cur];
+        a.phi = b->pool[4];
+        a.u_out = b->pool[b->cur ^ 1];
+        a.v_out = b->pool[2 + (b->cur ^ 1)];
+        a.sims = b->d_sims;
+        a.items = items;
+        a.flags = b->d_flags;
+        a.nitems = cnt;
+        a.per_xcd = ((cnt + 3) / 4 + 7) / 8;
+        *e = rdc::launch_batch_stream(a, k, s);
+        return RDC_OK;
+    }
+    const rdc::Item* items = nullptr;
+    const rdc_status st = items_for(b, k, tile_rows_of(b), &items, &cnt);
+    if (st != RDC_OK) return st;
+    *e = rdc::batch_launch_any(batch_args(b, items, cnt), k, tile_rows_of(b), s);
+    return RDC_OK;
+}
+
+
 // Steps per launch for advancing n steps: ceil(n/T) launches of near-equal
 // length (a short remainder launch would pay a whole tile load and store for
 // a step or two); with `even`, one launch more when that count is odd, so the
@@ -336,11 +414,8 @@ rdc_status run_launches(rdc_batch* b, const std::vector<int>& ks, int64_t n, hip
     rdc_status st = RDC_OK;
     if (tiled && e == hipSuccess) {
         for (const int k : ks) {
-            const rdc::Item* items = nullptr;
-            int cnt = 0;
-            st = items_for(b, k, b->rows, &items, &cnt);
+            st = launch_tiled(b, k, s, &e);
             if (st != RDC_OK) break;
-            e = rdc::batch_launch_any(batch_args(b, items, cnt), k, b->rows, s);
             if (e != hipSuccess) {
                 what = "batched step launch";
                 break;
@@ -402,6 +477,8 @@ rdc_status set_resident(rdc_batch* b, int32_t max_cells) {
     if (b->d_res) (void)hipFree(b->d_res);
     for (auto& kv : b->items) (void)hipFree(kv.second.first);
     b->items.clear();
+    for (auto& kv : b->sitems) (void)hipFree(kv.second.first);
+    b->sitems.clear();
     b->d_res = d;
     b->nres = static_cast<int>(list.size());
     ++b->plan;
@@ -435,6 +512,8 @@ void release(rdc_batch* b) {
     if (b->side) (void)hipStreamSynchronize(b->side);
     for (auto& kv : b->items) (void)hipFree(kv.second.first);
     b->items.clear();
+    for (auto& kv : b->sitems) (void)hipFree(kv.second.first);
+    b->sitems.clear();
     if (b->d_res) (void)hipFree(b->d_res);
     if (b->d_sims) (void)hipFree(b->d_sims);
     if (b->d_flags) (void)hipFree(b->d_flags);
@@ -541,7 +620,10 @@ int32_t rdc_batch_resident_count(const rdc_batch* b) { return b ? b->nres : -1; 
 rdc_status rdc_batch_set_block(rdc_batch* b, int32_t T, int32_t rows) {
     if (!b) return RDC_E_INVAL;
     if (T < 1 || T > rdc::kMaxBlock) return bfail(b, RDC_E_INVAL, "T must be in 1..12");
-    if (rows != 48 && rows != 56 && rows != 64) return bfail(b, RDC_E_INVAL, "rows must be 48, 56 or 64");
+    if (rows != 48 && rows != 56 && rows != 64 && rows != RDC_TILE_STREAM)
+        return bfail(b, RDC_E_INVAL, "rows must be 48, 56, 64 or RDC_TILE_STREAM");
+    if (rows == RDC_TILE_STREAM && T > rdc::kMaxStream)
+        return bfail(b, RDC_E_INVAL, "the row pipelines take at most 11 steps per launch");
     b->T = T;
     b->rows = rows;
     return RDC_OK;
@@ -658,9 +740,7 @@ rdc_status rdc_batch_capture(rdc_batch* b, int64_t n, rdc_graph** out) {
     Dev g(b->device);
     // Work-item tables are made before capture: nothing allocates inside it.
     for (const int k : ks) {
-        const rdc::Item* items = nullptr;
-        int cnt = 0;
-        rdc_status s = items_for(b, k, b->rows, &items, &cnt);
+        rdc_status s = tables_for(b, k);
         if (s != RDC_OK) return s;
     }
     hipStream_t cs = nullptr;

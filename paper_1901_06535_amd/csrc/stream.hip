@@ -31,6 +31,10 @@
 // outstanding loads exactly and wait only for the row a level is about to
 // use.  Waves whose strip reaches past a domain edge take a second copy of
 // the loop that loads and stores cell by cell.
+#include <algorithm>
+#include <vector>
+
+#include "batch.h"
 #include "kernels.h"
 #include "tile.h"
 
@@ -304,26 +308,21 @@ __device__ __forceinline__ void stream_pipeline(const StepArgs<float>& a, const 
     }
 }
 
-template <int T, bool MIRROR>
-__global__ __launch_bounds__(kStreamWaves * 64, 2)
-void k_stream(StepArgs<float> a, StreamGeom g) {
-    static_assert(stream_fits<T>(), "T too large for the row slots");
-    __shared__ float4 phs[kStreamWaves][kPhiRows][64];   // each wave's c1*phi ring
-    constexpr int HX = stream_hx<T>();
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // Workgroups are dealt to the 8 XCDs round-robin: renumber so that each
-    // XCD takes a contiguous run of work items (neighbouring strips of the
-    // same rows, whose halo columns then meet in that XCD's L2).
-    const int b = blockIdx.x;
-    const int wg = (b & 7) * g.per_xcd + (b >> 3);
-    const int item = wg * kStreamWaves + wave;
-    if (item >= g.items) return;
-    const int strip = item % g.nstrips;
-    const int seg = item / g.nstrips;
-    const int nx = a.nx;
+// Output columns per strip: the loaded 256 less the left halo and a right
+// halo of at least T, kept a multiple of 4.
+template <int T>
+constexpr int stream_bx() { return (256 - stream_hx<T>() - T) & ~3; }
 
-    const int x_out0 = strip * g.bx;           // first output column
+// One wave's work item: output columns [strip * bx, strip * bx + bx) and
+// output rows [y0, y1) of the grid `a` describes.
+template <int T, bool MIRROR>
+__device__ __forceinline__ void stream_wave(const StepArgs<float>& a, int strip, int y0, int y1,
+                                            float4 (&phs)[kPhiRows][64]) {
+    constexpr int HX = stream_hx<T>();
+    constexpr int bx = stream_bx<T>();
+    const int lane = threadIdx.x & 63;
+    const int nx = a.nx;
+    const int x_out0 = strip * bx;             // first output column
     const int x_load0 = x_out0 - HX;           // first loaded column
     Lane ln;
     ln.gx = x_load0 + 4 * lane;
@@ -342,34 +341,85 @@ void k_stream(StepArgs<float> a, StreamGeom g) {
             ln.rev = true;
         }
     }
-    const bool out_lane = lane >= HX / 4 && lane < (HX + g.bx) / 4 && ln.gx < nx;
+    const bool out_lane = lane >= HX / 4 && lane < (HX + bx) / 4 && ln.gx < nx;
     ln.so4 = out_lane ? 4 * ln.gx : kOff;
 #pragma unroll
     for (int c = 0; c < 4; ++c) ln.so[c] = out_lane && ln.gx + c < nx ? 4 * (ln.gx + c) : kOff;
     ln.out = __builtin_amdgcn_ballot_w64(out_lane);
 
-    const int y0 = seg * g.seg_rows;
-    const int y1 = min(y0 + g.seg_rows, a.ny);   // output rows [y0, y1)
     const bool inside = x_load0 >= 0 && x_load0 + 256 <= nx;
     if (MIRROR) {
-        stream_pipeline<T, kMirror>(a, ln, y0, y1, phs[wave], !inside);
+        stream_pipeline<T, kMirror>(a, ln, y0, y1, phs, !inside);
     } else {
         // Interior strips load and store 16-byte words; a strip that reaches
         // past the left or right edge goes cell by cell.
         if (inside)
-            stream_pipeline<T, kInterior>(a, ln, y0, y1, phs[wave], false);
+            stream_pipeline<T, kInterior>(a, ln, y0, y1, phs, false);
         else
-            stream_pipeline<T, kCells>(a, ln, y0, y1, phs[wave], true);
+            stream_pipeline<T, kCells>(a, ln, y0, y1, phs, true);
     }
+}
+
+template <int T, bool MIRROR>
+__global__ __launch_bounds__(kStreamWaves * 64, 2)
+void k_stream(StepArgs<float> a, StreamGeom g) {
+    static_assert(stream_fits<T>(), "T too large for the row slots");
+    __shared__ float4 phs[kStreamWaves][kPhiRows][64];   // each wave's c1*phi ring
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Workgroups are dealt to the 8 XCDs round-robin: renumber so that each
+    // XCD takes a contiguous run of work items (neighbouring strips of the
+    // same rows, whose halo columns then meet in that XCD's L2).
+    const int b = blockIdx.x;
+    const int wg = (b & 7) * g.per_xcd + (b >> 3);
+    const int item = wg * kStreamWaves + wave;
+    if (item >= g.items) return;
+    const int strip = item % g.nstrips;
+    const int seg = item / g.nstrips;
+    const int y0 = seg * g.seg_rows;
+    const int y1 = min(y0 + g.seg_rows, a.ny);   // output rows [y0, y1)
+    stream_wave<T, MIRROR>(a, strip, y0, y1, phs[wave]);
+}
+
+// Many grids of a batch (the pooled planes of batch.h): one wave per work
+// item (grid, strip, segment), every item's rows planned on the host; the
+// same pipeline as k_stream, so each grid evolves bit-identically to the
+// same grid stepped alone.  Edge strips go cell by cell (batch grids have
+// any width).
+template <int T>
+__global__ __launch_bounds__(kStreamWaves * 64, 2)
+void k_batch_stream(BatchStreamArgs b) {
+    static_assert(stream_fits<T>(), "T too large for the row slots");
+    __shared__ float4 phs[kStreamWaves][kPhiRows][64];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wg = (blockIdx.x & 7) * b.per_xcd + (blockIdx.x >> 3);
+    const int item = wg * kStreamWaves + wave;
+    if (item >= b.nitems) return;
+    const StreamItem it = b.items[item];
+    const SimDev sd = b.sims[it.sim];
+    StepArgs<float> a;
+    a.u = b.u + sd.offset;
+    a.v = b.v + sd.offset;
+    a.phi = b.phi + sd.offset;
+    a.u_out = b.u_out + sd.offset;
+    a.v_out = b.v_out + sd.offset;
+    a.arrival = nullptr;
+    a.tl = nullptr;
+    a.flag = b.flags + it.sim;
+    a.pitch = sd.pitch;
+    a.apitch = 0;
+    a.tpitch = 0;
+    a.tl_rate = 1;
+    a.nx = sd.nx;
+    a.ny = sd.ny;
+    a.step0 = 0;
+    a.theta = 0.0f;
+    a.k = sd.k;
+    stream_wave<T, false>(a, it.strip, it.y0, it.y1, phs[wave]);
 }
 
 template <int T>
 hipError_t stream_impl(const StepArgs<float>& a, hipStream_t s) {
-    constexpr int HX = stream_hx<T>();
-    // Output columns: the loaded 256 less the left halo HX and a right halo
-    // of at least T, kept a multiple of 4.
-    constexpr int bx = (256 - HX - T) & ~3;
-    const StreamGeom g = stream_geom(a.nx, a.ny, T, bx, stream_slots());
+    const StreamGeom g = stream_geom(a.nx, a.ny, T, stream_bx<T>(), stream_slots());
     const dim3 grid(8 * g.per_xcd), block(kStreamWaves * 64);
     if (a.nx % 4 == 0 && a.nx >= 256)
         hipLaunchKernelGGL((k_stream<T, true>), grid, block, 0, s, a, g);
@@ -380,9 +430,19 @@ hipError_t stream_impl(const StepArgs<float>& a, hipStream_t s) {
 
 }  // namespace
 
+// Work of one wave on a segment of `rows` output rows, in level-rows: T
+// levels on each of its rows + 2T - 2 ticks (at least the ramp bodies) less
+// the T(T-1) the ramp leaves out, about half a level per tick for its loads
+// and stores, and two ticks for the first rows' load latency.
+static double wave_cost(int rows, int T) {
+    const int64_t ticks = max(rows + 2 * T - 2, (2 * T - 2 + kUnroll - 1) / kUnroll * kUnroll);
+    return (T + 0.5) * ticks - (double)T * (T - 1) + 2.0 * T;
+}
+
 // Items (strip, segment) for the streaming kernel: strips of `bx` output
-// columns; segments of near-equal height, as many as keep lowest the rows
-// walked per round of resident waves (`slots` waves at a time).
+// columns; segments of near-equal height, as many as keep lowest the work
+// of the longest wave times the rounds of resident waves (`slots` waves at
+// a time).
 StreamGeom stream_geom(int nx, int ny, int T, int bx, int slots) {
     StreamGeom g{};
     g.bx = bx;
@@ -393,13 +453,7 @@ StreamGeom stream_geom(int nx, int ny, int T, int bx, int slots) {
         const int rows = (ny + nseg - 1) / nseg;
         const int64_t items = (int64_t)g.nstrips * ((ny + rows - 1) / rows);
         const int64_t rounds = (items + slots - 1) / slots;
-        // per wave, in level-rows: T levels on each of its rows + 2T - 2
-        // ticks (at least the ramp bodies) less the T(T-1) the ramp leaves
-        // out, about half a level per tick for its loads and stores, and two
-        // ticks for the first rows' load latency
-        const int64_t ticks = max(rows + 2 * T - 2, (2 * T - 2 + kUnroll - 1) / kUnroll * kUnroll);
-        const double cost =
-            (double)rounds * ((T + 0.5) * ticks - (double)T * (T - 1) + 2.0 * T);
+        const double cost = (double)rounds * wave_cost(rows, T);
         if (best < 0 || cost < best) {
             best = cost;
             best_rows = rows;
@@ -432,6 +486,48 @@ int stream_slots() {
 
 bool stream_supported(int T) { return T >= 2 && T <= kMaxStream; }
 
+std::vector<StreamItem> batch_stream_items(const std::vector<GridShape>& grids, int T,
+                                           int slots) {
+    std::vector<StreamItem> list;
+    const int bx = stream_strip_cols(T);
+    if (grids.empty() || bx <= 0 || slots < 1) return list;
+    int max_ny = 1;
+    for (const GridShape& g : grids) max_ny = max(max_ny, g.ny);
+    // The most rows a segment may have: every grid is cut into ceil(ny / h)
+    // segments of near-equal height (so none has more than h rows); h is
+    // the one that keeps lowest the work of the longest wave times the
+    // rounds of resident waves.
+    int best_h = max_ny;
+    double best = -1.0;
+    for (int h = max_ny; h >= 1; --h) {
+        int64_t items = 0;
+        for (const GridShape& g : grids)
+            items += (int64_t)((g.nx + bx - 1) / bx) * ((g.ny + h - 1) / h);
+        if (items > 64LL * slots) break;
+        const int64_t rounds = (items + slots - 1) / slots;
+        const double cost = (double)rounds * wave_cost(h, T);
+        if (best < 0 || cost <= best) {
+            best = cost;
+            best_h = h;
+        }
+    }
+    for (const GridShape& g : grids) {
+        const int nseg = (g.ny + best_h - 1) / best_h;
+        const int rows = (g.ny + nseg - 1) / nseg;
+        const int nstrips = (g.nx + bx - 1) / bx;
+        for (int y0 = 0; y0 < g.ny; y0 += rows)
+            for (int st = 0; st < nstrips; ++st)
+                list.push_back({g.sim, st, y0, min(y0 + rows, g.ny)});
+    }
+    // Longest first: with more items than resident waves, the rounds after
+    // the first are the short items (neighbouring strips of a segment stay
+    // together, so their halo columns meet in one XCD's L2).
+    std::stable_sort(list.begin(), list.end(), [](const StreamItem& a, const StreamItem& c) {
+        return a.y1 - a.y0 > c.y1 - c.y0;
+    });
+    return list;
+}
+
 hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s) {
     switch (T) {
         case 2: return stream_impl<2>(a, s);
@@ -444,6 +540,49 @@ hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s) {
         case 9: return stream_impl<9>(a, s);
         case 10: return stream_impl<10>(a, s);
         case 11: return stream_impl<11>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int stream_strip_cols(int T) {
+    switch (T) {
+        case 2: return stream_bx<2>();
+        case 3: return stream_bx<3>();
+        case 4: return stream_bx<4>();
+        case 5: return stream_bx<5>();
+        case 6: return stream_bx<6>();
+        case 7: return stream_bx<7>();
+        case 8: return stream_bx<8>();
+        case 9: return stream_bx<9>();
+        case 10: return stream_bx<10>();
+        case 11: return stream_bx<11>();
+        default: return 0;
+    }
+}
+
+namespace {
+template <int T>
+hipError_t batch_stream_impl(const BatchStreamArgs& b, hipStream_t s) {
+    const int wgs = (b.nitems + kStreamWaves - 1) / kStreamWaves;
+    if (b.nitems < 1 || b.per_xcd * 8 < wgs) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_batch_stream<T>), dim3(8 * b.per_xcd), dim3(kStreamWaves * 64), 0, s,
+                       b);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_batch_stream(const BatchStreamArgs& b, int T, hipStream_t s) {
+    switch (T) {
+        case 2: return batch_stream_impl<2>(b, s);
+        case 3: return batch_stream_impl<3>(b, s);
+        case 4: return batch_stream_impl<4>(b, s);
+        case 5: return batch_stream_impl<5>(b, s);
+        case 6: return batch_stream_impl<6>(b, s);
+        case 7: return batch_stream_impl<7>(b, s);
+        case 8: return batch_stream_impl<8>(b, s);
+        case 9: return batch_stream_impl<9>(b, s);
+        case 10: return batch_stream_impl<10>(b, s);
+        case 11: return batch_stream_impl<11>(b, s);
         default: return hipErrorInvalidValue;
     }
 }

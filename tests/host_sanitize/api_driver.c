@@ -276,6 +276,19 @@ static void batch(void) {
     EXPECT(rdc_batch_capture(bt, 10, &g) == RDC_OK && g);
     EXPECT(rdc_graph_launch(g) == RDC_OK);
     EXPECT(rdc_graph_destroy(g) == RDC_OK);
+    /* row pipelines: 20 steps at T = 6 in 4 launches of 5; a one-step call on the tiles */
+    EXPECT(rdc_batch_set_block(bt, 12, RDC_TILE_STREAM) == RDC_E_INVAL);
+    EXPECT(rdc_batch_set_block(bt, 6, RDC_TILE_STREAM) == RDC_OK);
+    l0 = shim_launches();
+    EXPECT(rdc_batch_step(bt, 20) == RDC_OK);
+    EXPECT(shim_launches() - l0 == 4);
+    l0 = shim_launches();
+    EXPECT(rdc_batch_step(bt, 1) == RDC_OK);
+    EXPECT(shim_launches() - l0 == 1);
+    EXPECT(rdc_batch_capture(bt, 12, &g) == RDC_OK && g);
+    EXPECT(rdc_graph_launch(g) == RDC_OK);
+    EXPECT(rdc_graph_destroy(g) == RDC_OK);
+    EXPECT(rdc_batch_set_block(bt, 6, 48) == RDC_OK);
     EXPECT(rdc_batch_resident_count(NULL) == -1);
     void *cu = NULL, *cv = NULL;
     EXPECT(rdc_batch_current(bt, &cu, &cv) == RDC_OK && cu && cv);

@@ -52,7 +52,11 @@ def _single(spec, state, disk, T, nsteps):
     return out
 
 
-@pytest.mark.parametrize("T,rows", [(8, 56), (5, 48), (8, 64), (1, 56), (12, 48), (10, 64)])
+STREAM = rdc.RDC_TILE_STREAM
+
+
+@pytest.mark.parametrize("T,rows", [(8, 56), (5, 48), (8, 64), (1, 56), (12, 48), (10, 64),
+                                    (8, STREAM), (11, STREAM), (3, STREAM), (1, STREAM)])
 def test_batch_equals_single_grids_bitwise(T, rows):
     specs, states, disks = _case()
     b = _batch(specs, states, disks, T, rows)
@@ -62,6 +66,46 @@ def test_batch_equals_single_grids_bitwise(T, rows):
         ref = _single(specs[i], states[i], disks[i], 1, 37)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (i, SIZES[i])
     b.close()
+
+
+@pytest.mark.parametrize("T", [2, 5, 8, 11])
+def test_batch_row_pipelines_on_every_grid_bitwise(T):
+    """The whole-grid path off, so every grid of the batch (1 x 1, 5 x 300,
+    17 x 17 up to 200 x 333) runs on the batched row pipelines: one wave per
+    (grid, strip, segment), segments planned over all grids; launches of
+    exactly T steps and a shorter one; every grid bit-identical to the one-
+    step kernel on it alone."""
+    specs, states, disks = _case(seed=13)
+    b = _batch(specs, states, disks, T, STREAM)
+    b.set_resident(0)
+    assert b.resident_count() == 0
+    n = 3 * T + (T - 1 if T > 2 else 0)
+    b.step(n)
+    for i in range(len(specs)):
+        got = b.read(i)
+        ref = _single(specs[i], states[i], disks[i], 1, n)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (i, SIZES[i])
+    b.close()
+
+
+def test_batch_row_pipeline_graph_replays_equal_eager_steps():
+    specs, states, disks = _case(seed=15)
+    eager = _batch(specs, states, disks, 10, STREAM)
+    graph_b = _batch(specs, states, disks, 10, STREAM)
+    for x in (eager, graph_b):
+        x.set_resident(0)
+    g = graph_b.capture(40)          # 4 launches of 10
+    for rep in range(3):
+        eager.step(40)
+        g.launch()
+        graph_b.synchronize()
+        for i in range(len(specs)):
+            a = eager.read(i)
+            c = graph_b.read(i)
+            assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1]), (rep, i)
+    g.close()
+    eager.close()
+    graph_b.close()
 
 
 def test_batch_graph_replays_equal_eager_steps():
