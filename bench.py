@@ -437,14 +437,23 @@ def bench_batch(args, small=False):
         "value": round(single, 2), "unit": "GCell-updates/s", "seconds": round(t_single, 3),
         "wall_s": round(wall_single, 3), "speedup": round(value / single, 2),
         "finite_grids_bitwise_equal": "%d/%d" % (same, len(sims) - len(diverged))}
-    roof = None
+    ach = 21.0 * cells * steps * args.steps / t / 1e12
     if resident == len(sims):
         # one whole-grid launch per run: ALU-bound (no HBM traffic between steps)
-        ach = 21.0 * cells * steps * args.steps / t / 1e12
         roof = {"bound": "alu", "achieved": round(ach, 2), "peak": 78.6, "unit": "TFLOP/s",
                 "frac": round(ach / 78.6, 4), "traffic": None, "kernel": "k_batch_resident",
                 "launch_ms": round(1e3 * t / args.steps, 3),
                 "algorithmic": "21 FLOP/update x %d cells x %d steps per launch" % (cells, steps)}
+    else:
+        # the whole graph replay (batched T-step launches, the small grids'
+        # whole-grid launch beside them): the run's FLOP rate
+        roof = {"bound": "alu", "achieved": round(ach, 2), "peak": 78.6, "unit": "TFLOP/s",
+                "frac": round(ach / 78.6, 4), "traffic": None,
+                "kernel": "whole run (%s, k_batch_resident)"
+                          % ("k_batch_stream<T=%d>" % T if rows == 1 else
+                             "k_batch_stepT<T=%d,rows=%d>" % (T, rows)),
+                "run_ms": round(1e3 * t / args.steps, 3),
+                "algorithmic": "21 FLOP/update x %d cells x %d steps per run" % (cells, steps)}
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GCell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t / args.steps, 3),
