@@ -12,10 +12,14 @@
 //   - each level t keeps the three rows of u^(t-1) its five-node sum needs
 //     (row index mod 3; level 1 keeps u^0 rows mod 6 to leave room for the
 //     loads in flight),
-//   - v and c1*phi of the rows in flight sit in 12 row slots (row index mod
-//     12); each level updates v in place as the row passes it.
+//   - v of the rows in flight sits in 12 row slots (row index mod 12); each
+//     level updates it in place as the row passes it.
+// c1*phi of the rows in flight is kept in a per-wave LDS ring of 16 rows.
 // The tick loop is unrolled by 12, so every slot index is a compile-time
-// constant and no value is ever moved between registers.  There are no LDS
+// constant and no value is ever moved between registers.  A wave's first
+// 2T - 2 ticks (where level t has no row of its range before tick 2t - 2)
+// are loop bodies of their own that leave those levels out, and its last,
+// partial body a copy that stops after the last tick.  There are no LDS
 // tiles and no barriers: waves run independently.  East / west neighbours
 // cross lanes by DPP; the strip's outer columns are a halo of width >= T
 // that goes stale by one column per level and is recomputed by the
@@ -29,8 +33,11 @@
 // (rows past the segment and lanes outside the output use buffer offsets
 // past the row's end, which the hardware drops), so the compiler can count
 // outstanding loads exactly and wait only for the row a level is about to
-// use.  Waves whose strip reaches past a domain edge take a second copy of
-// the loop that loads and stores cell by cell.
+// use.  Waves whose strip reaches past a domain edge load mirrored 16-byte
+// blocks and put their cells in order on first use, where the width is a
+// multiple of 4 (and at least 256); otherwise they take a second copy of the
+// loop that loads and stores cell by cell.  The same pipeline also runs the
+// grids of a batch (k_batch_stream: one wave per grid, strip and segment).
 #include <algorithm>
 #include <vector>
 

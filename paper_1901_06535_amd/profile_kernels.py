@@ -19,7 +19,8 @@ turns the two counter runs' CSV files into per-launch HBM bytes: each
 kernel's average FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what
 the same counters read for the 1 GiB copy, merged into profiles/traffic.json
 under keys naming the kernel and the grid, with the hash of the stepper's
-kernel sources (readers ignore entries taken on other sources), and printed
+kernel sources, comments and layout aside (readers ignore entries taken on
+other code), and printed
 as a table;
 
     python3 -m paper_1901_06535_amd.profile_kernels --stats KERNEL_STATS.csv
@@ -50,12 +51,24 @@ STEPPER_SOURCES = ("cell.h", "tile.h", "kernels.h", "kernels.hip", "stream.hip",
                    "tiles_impl.h")
 
 
+def code_text(src: str) -> str:
+    """A source's text with its comments removed and every run of white
+    space made one space: what the compiler sees, so that an edit of a
+    comment or of the layout does not orphan counters taken on the same
+    code."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def source_hash() -> str:
-    """Hash of the sources the stepper kernels are compiled from."""
+    """Hash of the code (comments and layout aside) of the sources the
+    stepper kernels are compiled from."""
     h = hashlib.sha256()
     for f in STEPPER_SOURCES:
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 
