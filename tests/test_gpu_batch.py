@@ -88,6 +88,34 @@ def test_batch_row_pipelines_on_every_grid_bitwise(T):
     b.close()
 
 
+@pytest.mark.parametrize("T", [8, 11])
+def test_batch_row_pipelines_in_several_rounds_bitwise(T):
+    """600 grids of 300 x 200 and 257 x 190 (two strips each): one round of
+    resident waves would leave every grid a single 200-row segment, so the
+    plan cuts them into 40-row segments, 6,000 items in three rounds of
+    waves, longest first.  Every grid bit-identical to the same batch
+    stepped one step per launch on tiles."""
+    specs, states = [], []
+    rng = np.random.default_rng(21)
+    for i in range(600):
+        nx, ny = (300, 200) if i % 2 == 0 else (257, 190)
+        p = dict(inputs.PARAMS_WORKLOAD)
+        p["eps"] = float(rng.uniform(0.024, 0.03))
+        specs.append((nx, ny, p))
+        states.append(inputs.random_state(nx, ny, seed=500 + i, umax=0.02, vmax=0.02))
+    disks = [(i, specs[i][0] // 2, specs[i][1] // 3, 4) for i in range(0, 600, 7)]
+    runs = []
+    for shape in ((T, STREAM), (1, 56)):
+        print("[case] batch of 600, T=%d rows=%d" % shape, flush=True)
+        b = _batch(specs, states, disks, *shape)
+        b.set_resident(0)
+        b.step(3 * T - 1)
+        runs.append([b.read(i) for i in range(len(specs))])
+        b.close()
+    for i, (a, c) in enumerate(zip(*runs)):
+        assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1]), i
+
+
 def test_batch_row_pipeline_graph_replays_equal_eager_steps():
     specs, states, disks = _case(seed=15)
     eager = _batch(specs, states, disks, 10, STREAM)
