@@ -30,7 +30,8 @@ prints the top rows of a rocprofv3 --stats kernel table, and
     python3 -m paper_1901_06535_amd.profile_kernels --valu COUNTERS.csv
 
 the VALU instruction counts and busy fraction of one --pmc run of the
-counters in VALU_COUNTERS.
+counters in VALU_COUNTERS, and ``--valu-active`` the VALU busy fraction by
+time of one run of ACTIVE_COUNTERS.
 """
 from __future__ import annotations
 
@@ -112,6 +113,38 @@ def stats(path: str, top: int = 20) -> None:
 
 
 VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_INSTS_LDS", "GRBM_GUI_ACTIVE")
+
+
+# VALU time: cycles the SIMDs spend executing VALU instructions (quad-cycles,
+# so multi-cycle instructions count as long as they run), the FP32
+# transcendental instructions among them, and the waves' waiting time.
+ACTIVE_COUNTERS = ("SQ_ACTIVE_INST_VALU", "SQ_INSTS_VALU", "SQ_INSTS_VALU_TRANS_F32",
+                   "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES",
+                   "GRBM_GUI_ACTIVE")
+
+
+def valu_active(path: str, cus: int = 256, xcds: int = 8) -> None:
+    """Per-dispatch averages of one rocprofv3 --pmc run of ACTIVE_COUNTERS for
+    each stepper kernel: VALU busy by time = SQ_ACTIVE_INST_VALU (quad-cycles
+    summed over the SIMDs) / (GRBM_GUI_ACTIVE / xcds * cus), next to the
+    issue count's 4-cycle estimate; the quad-cycles beyond one per issued
+    instruction, per transcendental instruction; and the fraction of wave
+    cycles spent waiting to issue."""
+    m = {c: _counter_means(path, c) for c in ACTIVE_COUNTERS}
+    for k in sorted(m["SQ_ACTIVE_INST_VALU"]):
+        if not k.startswith("k_st") and k != "k_copy16":
+            continue
+        g = lambda c: m[c].get(k, (float("nan"), 0))[0]
+        gui = g("GRBM_GUI_ACTIVE") / xcds * cus
+        act, ins, tr = g("SQ_ACTIVE_INST_VALU"), g("SQ_INSTS_VALU"), g("SQ_INSTS_VALU_TRANS_F32")
+        # (FP64 kernels' reciprocals are not FP32 transcendentals)
+        extra = (act - ins) / tr if tr > 0.01 * ins else float("nan")
+        print("%-30s VALU_active=%.4g insts=%.4g trans_f32=%.4g -> VALU busy by time %.1f%% "
+              "(issue count x 4 cycles: %.1f%%), extra quad-cycles per transcendental %.2f, "
+              "waiting %.0f%% of wave cycles (LDS %.1f%%)"
+              % (k, act, ins, tr, 100 * act / gui, 100 * ins / gui, extra,
+                 100 * g("SQ_WAIT_INST_ANY") / g("SQ_WAVE_CYCLES"),
+                 100 * g("SQ_WAIT_INST_LDS") / g("SQ_WAVE_CYCLES")))
 
 
 def valu(path: str, cus: int = 256, xcds: int = 8) -> None:
@@ -206,6 +239,7 @@ def main():
     ap.add_argument("--summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--stats", metavar="KERNEL_STATS_CSV")
     ap.add_argument("--valu", metavar="COUNTER_CSV")
+    ap.add_argument("--valu-active", metavar="COUNTER_CSV")
     ap.add_argument("--top", type=int, default=20)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "profiles",
                                                   "traffic.json"))
@@ -216,6 +250,8 @@ def main():
         return stats(args.stats, args.top)
     if args.valu:
         return valu(args.valu)
+    if args.valu_active:
+        return valu_active(args.valu_active)
     log = []
     n = GRIDS[args.workload]
     if args.workload == "circuit":
