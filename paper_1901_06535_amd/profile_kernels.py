@@ -48,8 +48,8 @@ import numpy as np
 from . import inputs, rdc
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STEPPER_SOURCES = ("cell.h", "tile.h", "kernels.h", "kernels.hip", "stream.hip", "stream64.hip",
-                   "tiles_impl.h")
+STEPPER_SOURCES = ("cell.h", "tile.h", "kernels.h", "kernels.hip", "stream_pipe.h", "stream.hip",
+                   "stream64.hip", "tiles_impl.h")
 
 
 def code_text(src: str) -> str:
@@ -64,11 +64,15 @@ def code_text(src: str) -> str:
 
 def source_hash() -> str:
     """Hash of the code (comments and layout aside) of the sources the
-    stepper kernels are compiled from."""
+    stepper kernels are compiled from, and of their per-source compiler
+    flags."""
+    from .build import SOURCE_FLAGS
     h = hashlib.sha256()
     for f in STEPPER_SOURCES:
         with open(os.path.join(HERE, "csrc", f), encoding="utf-8") as fh:
             h.update(code_text(fh.read()).encode())
+        h.update(b"\0")
+        h.update(" ".join(SOURCE_FLAGS.get(f, [])).encode())
         h.update(b"\0")
     return h.hexdigest()[:16]
 
