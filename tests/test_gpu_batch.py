@@ -192,9 +192,15 @@ def test_batch_matches_oracle_per_grid():
     b.close()
 
 
-def test_batch_nonfinite_flag_is_per_grid():
+@pytest.mark.parametrize("path", ["whole_grid", "tiles", "row_pipelines"])
+def test_batch_nonfinite_flag_is_per_grid(path):
+    """u = -q planted in one cell of grid 1 makes (u - q)/(u + q) infinite:
+    only grid 1's flag is raised, on each path the grids can take."""
     specs, states, disks = _case(seed=4)
     b = rdc.BatchSim(specs[:3])
+    if path != "whole_grid":
+        b.set_resident(0)
+        b.set_block(8, 56 if path == "tiles" else STREAM)
     for i in range(3):
         b.set_phi(i, states[i][2])
         b.write(i, states[i][0], states[i][1])
