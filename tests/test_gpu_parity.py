@@ -302,8 +302,11 @@ def test_stimulation_matches_oracle_at_edges():
     s.close()
 
 
-@pytest.mark.parametrize("dtype,T", [("fp32", 1), ("fp32", 8), ("fp64", 1)])
-def test_nonfinite_flag_is_raised_and_cleared(dtype, T):
+@pytest.mark.parametrize("dtype,T,rows", [("fp32", 1, 0), ("fp32", 8, 0), ("fp64", 1, 0),
+                                          ("fp32", 8, rdc.RDC_TILE_STREAM),
+                                          ("fp32", 11, rdc.RDC_TILE_STREAM),
+                                          ("fp64", 8, rdc.RDC_TILE_STREAM)])
+def test_nonfinite_flag_is_raised_and_cleared(dtype, T, rows):
     nx = ny = 40
     q = inputs.PARAMS_WORKLOAD["q"]
     u = np.zeros((ny, nx), np.float32)
@@ -312,6 +315,8 @@ def test_nonfinite_flag_is_raised_and_cleared(dtype, T):
     s = rdc.Sim(nx, ny, inputs.PARAMS_WORKLOAD, dtype)
     s.set_phi(np.full((ny, nx), 0.054, np.float32))
     s.set_block(T)
+    if rows:
+        s.set_tile_rows(rows)
     s.write(u, v)
     s.step(16)
     _, _ = s.read(allow_nonfinite=True)
