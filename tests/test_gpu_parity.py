@@ -358,8 +358,12 @@ def test_split_run_resume_and_repeat_are_bitwise():
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
 
 
+@pytest.mark.parametrize("T,rows", [(8, 0), (11, rdc.RDC_TILE_STREAM)])
 @pytest.mark.parametrize("sym", ["xflip", "yflip", "transpose"])
-def test_fp32_d4_symmetry_is_bitwise(sym):
+def test_fp32_d4_symmetry_is_bitwise(sym, T, rows):
+    """A symmetric phi map and stimuli give a bitwise symmetric field, on the
+    LDS tiles and on the row pipelines (300 columns: edge strips of mirrored
+    16-byte blocks)."""
     n = 300
     _, _, phi = inputs.random_state(n, n, seed=8)
     half = n // 2
@@ -375,7 +379,9 @@ def test_fp32_d4_symmetry_is_bitwise(sym):
     s = rdc.Sim(n, n, inputs.PARAMS_WORKLOAD, "fp32")
     s.set_phi(np.ascontiguousarray(phi))
     s.write(np.zeros((n, n), np.float32), np.zeros((n, n), np.float32))
-    s.set_block(8)
+    s.set_block(T)
+    if rows:
+        s.set_tile_rows(rows)
     s.stimulate(disks)
     s.step(1500)
     u, v = s.read()
