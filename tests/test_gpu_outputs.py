@@ -55,11 +55,15 @@ def test_fp64_timelapse_bitwise_equals_oracle(rate, T):
     assert np.array_equal(arr, r2.arrival)
 
 
-@pytest.mark.parametrize("T,rows", [(3, 48), (8, 56), (8, 80), (5, 64)])
+@pytest.mark.parametrize("T,rows", [(3, 48), (8, 56), (8, 80), (5, 64),
+                                    (11, rdc.RDC_TILE_STREAM)])
 @pytest.mark.parametrize("rate", [1, 4, 5])
 def test_fp32_timelapse_is_launch_shape_invariant(T, rows, rate):
     """Every (T, tile height) gives the one-step kernel's timelapse bit for
-    bit, also when the rate does not divide T and around the stimulus split."""
+    bit, also when the rate does not divide T and around the stimulus split
+    (with the row pipelines chosen, the steps before the timelapse is
+    attached run on them, and the launches while it records on the LDS
+    tiles)."""
     nx, ny = 333, 275
     u, v, phi = _state(nx, ny, 37)
     out = []
