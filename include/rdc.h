@@ -152,8 +152,9 @@ rdc_status rdc_set_block(rdc_ctx *ctx, int32_t T);
  * depend on it): 0 (auto: LDS tiles of 56 rows), one of the LDS tile heights
  * 48, 56, 64, 80, or RDC_TILE_STREAM: every wave walks a strip of 256
  * (FP32) or 128 (FP64) columns down a segment of rows, carrying all T steps
- * of each row in registers (FP32 T = 2..11, FP64 T = 2..8; launches with an
- * arrival map or timelapse attached use 56-row tiles).  The Python
+ * of each row in registers (FP32 T = 2..11, and 12 on grids whose width is
+ * a multiple of 4 and at least 256; FP64 T = 2..8; other launches, and those
+ * with an arrival map or timelapse attached, use 56-row tiles).  The Python
  * autotuner times the choices on the grid's shape.  Errors: RDC_E_INVAL. */
 #define RDC_TILE_STREAM 1
 rdc_status rdc_set_tile_rows(rdc_ctx *ctx, int32_t rows);

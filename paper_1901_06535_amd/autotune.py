@@ -24,8 +24,11 @@ from .profile_kernels import source_hash
 DEFAULT_T = (4, 6, 8, 9, 10, 11, 12)
 # LDS tile heights, and 1 = the row-pipeline kernel (rdc.RDC_TILE_STREAM)
 DEFAULT_ROWS = (48, 56, 64, 80, 1)
-# Most steps per launch the row-pipeline kernels take, per precision.
-MAX_T_STREAM = {"fp32": 11, "fp64": 8}
+# Most steps per launch the row-pipeline kernels take, per precision (FP32:
+# 12 on grids whose width is a multiple of 4 and at least 256; on other
+# grids such launches run on LDS tiles), and the batched ones.
+MAX_T_STREAM = {"fp32": 12, "fp64": 8}
+MAX_T_BATCH_STREAM = 11
 # Most steps per launch the library's tile kernels take, per precision
 # (rdc_set_block; the batched kernels are FP32).
 MAX_T = {"fp32": 12, "fp64": 8}
@@ -145,7 +148,7 @@ def tune_batch(batch, Ts: Sequence[int] = DEFAULT_T, rows: Sequence[int] = (48, 
         scratch.set_resident(res)             # the same grids tiled as in `batch`
         Ts = [T for T in Ts if T <= MAX_T["fp32"]]
         (T, r), table = _search(scratch.step, scratch.set_block, scratch.stream, Ts, rows,
-                                launches)
+                                launches, MAX_T_BATCH_STREAM)
         scratch.close()
         rec = {"T": T, "rows": r, "us_per_step": round(1e6 * table["T%d_r%d" % (T, r)], 3),
                "table": {k: round(1e6 * v, 3) for k, v in table.items()}}

@@ -319,7 +319,7 @@ rdc_status rdc_step(rdc_ctx* c, int64_t n) {
             e = f64 ? rdc::launch_step1(step_args<double>(c), c->stream)
                     : rdc::launch_step1(step_args<float>(c), c->stream);
         else if (rows == RDC_TILE_STREAM && !c->arrival && !c->tl &&
-                 (f64 ? rdc::stream64_supported(k) : rdc::stream_supported(k)))
+                 (f64 ? rdc::stream64_supported(k) : rdc::stream_supported(k, c->nx)))
             e = f64 ? rdc::launch_stream(step_args<double>(c), k, c->stream)
                     : rdc::launch_stream(step_args<float>(c), k, c->stream);
         else

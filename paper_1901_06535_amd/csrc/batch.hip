@@ -305,7 +305,7 @@ rdc_status stream_items_for(rdc_batch* b, int T, const rdc::StreamItem** out, in
 
 // Whether a launch of k steps runs on the row pipelines (else on tiles).
 bool stream_launch(const rdc_batch* b, int k) {
-    return b->rows == RDC_TILE_STREAM && rdc::stream_supported(k);
+    return b->rows == RDC_TILE_STREAM && k >= 2 && k <= rdc::kMaxStreamCells;
 }
 
 // Tile height of the tiled launches (the row pipelines' batches take 56-row
@@ -622,7 +622,7 @@ rdc_status rdc_batch_set_block(rdc_batch* b, int32_t T, int32_t rows) {
     if (T < 1 || T > rdc::kMaxBlock) return bfail(b, RDC_E_INVAL, "T must be in 1..12");
     if (rows != 48 && rows != 56 && rows != 64 && rows != RDC_TILE_STREAM)
         return bfail(b, RDC_E_INVAL, "rows must be 48, 56, 64 or RDC_TILE_STREAM");
-    if (rows == RDC_TILE_STREAM && T > rdc::kMaxStream)
+    if (rows == RDC_TILE_STREAM && T > rdc::kMaxStreamCells)
         return bfail(b, RDC_E_INVAL, "the row pipelines take at most 11 steps per launch");
     b->T = T;
     b->rows = rows;

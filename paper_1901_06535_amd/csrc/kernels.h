@@ -57,8 +57,13 @@ int tile_rows_default();
 
 // T forward-Euler steps per launch by register-resident row pipelines
 // (FP32, one wave per 256-column strip and segment of rows; no LDS tiles).
-// T in 2..kMaxStream; results bit-identical to launch_step1 and launch_stepT.
-constexpr int kMaxStream = 11;
+// T in 2..kMaxStreamCells on any grid, up to kMaxStream on grids whose
+// width is a multiple of 4 and at least 256 (edge strips of mirrored 16-byte
+// blocks; the cell-by-cell edge strips of other widths do not fit the
+// registers at T = 12); results bit-identical to launch_step1 and
+// launch_stepT.
+constexpr int kMaxStream = 12;
+constexpr int kMaxStreamCells = 11;
 struct StreamGeom {
     int bx;        // output columns per strip (a multiple of 4)
     int nstrips;   // strips across the grid
@@ -66,7 +71,7 @@ struct StreamGeom {
     int items;     // strips x segments, one wave each
     int per_xcd;   // workgroups per XCD
 };
-bool stream_supported(int T);
+bool stream_supported(int T, int nx);
 hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s);
 // The same for FP64 (128-column strips, 2 cells per lane), T in 2..kMaxStream64.
 constexpr int kMaxStream64 = 8;

@@ -30,10 +30,14 @@ template <int T>
 hipError_t stream_impl(const StepArgs<float>& a, hipStream_t s) {
     const StreamGeom g = stream_geom(a.nx, a.ny, T, stream_bx<T>(), stream_slots());
     const dim3 grid(8 * g.per_xcd), block(kStreamWaves * 64);
-    if (a.nx % 4 == 0 && a.nx >= 256)
+    if (a.nx % 4 == 0 && a.nx >= 256) {
         hipLaunchKernelGGL((k_stream<T, true>), grid, block, 0, s, a, g);
-    else
-        hipLaunchKernelGGL((k_stream<T, false>), grid, block, 0, s, a, g);
+    } else {
+        if constexpr (T > kMaxStreamCells)
+            return hipErrorInvalidValue;     // cell-by-cell edge strips: T <= 11
+        else
+            hipLaunchKernelGGL((k_stream<T, false>), grid, block, 0, s, a, g);
+    }
     return hipGetLastError();
 }
 
@@ -84,7 +88,9 @@ int stream_slots() {
     return cached;
 }
 
-bool stream_supported(int T) { return T >= 2 && T <= kMaxStream; }
+bool stream_supported(int T, int nx) {
+    return T >= 2 && (T <= kMaxStreamCells || (T <= kMaxStream && nx % 4 == 0 && nx >= 256));
+}
 
 hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s) {
     switch (T) {
@@ -98,6 +104,7 @@ hipError_t launch_stream(const StepArgs<float>& a, int T, hipStream_t s) {
         case 9: return stream_impl<9>(a, s);
         case 10: return stream_impl<10>(a, s);
         case 11: return stream_impl<11>(a, s);
+        case 12: return stream_impl<12>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

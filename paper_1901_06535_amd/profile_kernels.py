@@ -221,7 +221,7 @@ def summarize(fetch_csv: str, write_csv: str, out_json: str, workload: str) -> N
 
 
 TILE_CANDIDATES = [(T, r) for T in (4, 6, 8, 9, 10, 11, 12) for r in (48, 56, 64, 80)]
-STREAM_CANDIDATES = (4, 6, 8, 9, 10, 11)
+STREAM_CANDIDATES = (4, 6, 8, 9, 10, 11, 12)
 UNIFORM_TILES = [(8, 56), (8, 64), (10, 64), (11, 64), (12, 64)]
 CANDIDATES64 = [(8, 56), (8, 64), (8, 1)]
 LAUNCHES = 4

@@ -190,7 +190,7 @@ def test_circuit_arrival_over_the_whole_field(dtype, T, rows):
     assert bad_gpu == 0 and bad_ref == 0
 
 
-@pytest.mark.parametrize("T", [9, 11])
+@pytest.mark.parametrize("T", [9, 11, 12])
 def test_fp32_row_pipelines_equal_tiles_over_the_whole_field(case, T):
     name, wl, ref = case
     print("[case] fp32 row pipelines %s T=%d" % (name, T), flush=True)

@@ -197,7 +197,7 @@ def test_small_and_ragged_grids_fp32_launch_shapes(ny, nx):
     run.advance(19)
     assert masked_maxabs(ref[0], run.u) <= TOL
     for T, rows in ((3, 48), (8, 48), (3, rdc.RDC_TILE_STREAM), (8, rdc.RDC_TILE_STREAM),
-                    (11, rdc.RDC_TILE_STREAM)):
+                    (11, rdc.RDC_TILE_STREAM), (12, rdc.RDC_TILE_STREAM)):
         got = _run_fp32(u, v, phi, disks, T=T, rows=rows, nsteps=(20, 19))
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (T, rows)
 
@@ -214,7 +214,7 @@ def test_row_pipelines_across_strips_and_segments_bitwise(ny, nx):
     disks = [(nx // 2, ny // 2, 4), (3, 5, 3), (nx - 2, ny - 3, 5), (nx // 3, 1, 2)]
     ref = _run_fp32(u, v, phi, disks, T=1, rows=0, nsteps=(25, 18))
     assert np.isfinite(ref[0]).all()
-    for T in range(2, 12):
+    for T in range(2, 13):          # T = 12 on widths a multiple of 4 (>= 256), else tiles
         print_case("stream %dx%d T=%d" % (ny, nx, T))
         got = _run_fp32(u, v, phi, disks, T=T, rows=rdc.RDC_TILE_STREAM, nsteps=(25, 18))
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), T
@@ -227,13 +227,14 @@ def test_row_pipelines_on_tall_segments_bitwise(nx):
     the ramp bodies (where levels with no row yet are left out), whole loop
     bodies and a partial last one (at T = 2..4 the last segment is a single
     row: the ramp bodies only).  Each launch is exactly T steps; bit-identical
-    to the one-step kernel for T = 2..11, width a multiple of 4 (mirrored
-    16-byte edge blocks) and not (edge strips cell by cell)."""
+    to the one-step kernel for T = 2..12, width a multiple of 4 (mirrored
+    16-byte edge blocks) and not (edge strips cell by cell; there T = 12
+    runs on the LDS tiles)."""
     ny = 1024
     u, v, phi = inputs.random_state(nx, ny, seed=nx + 3, umax=0.02, vmax=0.02)
     disks = [(nx // 2, ny // 2, 4), (3, 5, 3), (nx - 2, ny - 3, 5), (nx // 3, 1, 2),
              (250, 30, 6), (nx - 300, 40, 6)]
-    for T in range(2, 12):
+    for T in range(2, 13):
         print_case("stream tall segments %dx%d T=%d" % (ny, nx, T))
         ref = _run_fp32(u, v, phi, disks, T=1, rows=0, nsteps=(2 * T, T))
         assert np.isfinite(ref[0]).all()
@@ -358,7 +359,7 @@ def test_split_run_resume_and_repeat_are_bitwise():
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
 
 
-@pytest.mark.parametrize("T,rows", [(8, 0), (11, rdc.RDC_TILE_STREAM)])
+@pytest.mark.parametrize("T,rows", [(8, 0), (11, rdc.RDC_TILE_STREAM), (12, rdc.RDC_TILE_STREAM)])
 @pytest.mark.parametrize("sym", ["xflip", "yflip", "transpose"])
 def test_fp32_d4_symmetry_is_bitwise(sym, T, rows):
     """A symmetric phi map and stimuli give a bitwise symmetric field, on the

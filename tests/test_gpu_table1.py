@@ -28,7 +28,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
 P1 = dict(inputs.PARAMS_TABLE1)
-FP32_SHAPES = [(1, 0), (8, 64), (8, rdc.RDC_TILE_STREAM), (11, rdc.RDC_TILE_STREAM)]
+FP32_SHAPES = [(1, 0), (8, 64), (8, rdc.RDC_TILE_STREAM), (11, rdc.RDC_TILE_STREAM),
+               (12, rdc.RDC_TILE_STREAM)]
 
 
 def _gpu(wl_u0, wl_v0, phi, params, dtype, T, rows, stimuli, steps, arrival=True):
