@@ -492,7 +492,7 @@ def bench_variants(args):
     res = {}
     for T, rows in ((1, 0), (8, 48), (8, 56), (8, 64), (10, 64), (11, 64), (12, 56), (12, 64),
                     (8, rdc.RDC_TILE_STREAM), (10, rdc.RDC_TILE_STREAM),
-                    (11, rdc.RDC_TILE_STREAM)):
+                    (11, rdc.RDC_TILE_STREAM), (12, rdc.RDC_TILE_STREAM)):
         sim.set_block(T)
         if rows:
             sim.set_tile_rows(rows)
